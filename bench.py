@@ -1,0 +1,209 @@
+"""Benchmark of the staggered-grid P_N time step on one MI355X.
+
+Workload: the P39 smooth-medium problem, 64^3 periodic cells, 1600 moments
+(p39_smooth in workloads.py).  A step is one full Strang step (odd half step,
+even full step, odd half step: three sweep launches) over the whole grid, with
+the state resident in HBM.  The metric is GDoF-updates/s = cells * moments *
+steps / seconds / 1e9 (the paper's MLCUP/s times 1e-3).
+
+Prints ONE JSON line.  `value` is the FP64 path; the FP32 path is timed on
+the same workload and reported in "fp32" together with its error against the
+FP64 GPU run.  The roofline object is for the dominant kernel (the odd sweep,
+launched twice per step): algorithmic bytes per launch over its mean launch
+time from HIP events on the library's stream.  cpu_baseline times the FP64
+CPU oracle on a bounded sample (a few steps of the same workload).
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+TABLE_BYTES = {1: 8 * 8, 0: 11 * 8}   # float64 table values read per cell: odd / even sweep
+ESZ = {"f64": 8, "f32": 4, "bf16": 2}
+
+
+def parity_counts(N):
+    V = (N + 1) ** 2
+    ve = sum(2 * l + 1 for l in range(0, N + 1, 2))
+    return V, ve, V - ve
+
+
+def sweep_bytes(N, ncell, esz, parity):
+    """Algorithmic HBM bytes of one sweep launch: dual moments read once,
+    target moments read and written once, plus the float64 tables."""
+    V, ve, vo = parity_counts(N)
+    tgt, dual = (vo, ve) if parity == 1 else (ve, vo)
+    return ncell * ((dual + 2 * tgt) * esz + TABLE_BYTES[parity])
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2004_02833_amd", "csrc")
+    for name in sorted(os.listdir(d)):
+        if name.endswith((".hip", ".h")):
+            h.update(open(os.path.join(d, name), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, workload, dtype):
+    """HBM bytes per launch from committed rocprofv3 PMC summaries, or None
+    when absent or taken on different kernel sources."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        data = json.load(open(path))
+        rec = data.get("%s/%s/%s" % (kernel, workload, dtype))
+        if rec and rec.get("source_hash") == kernel_source_hash():
+            return rec["bytes_per_launch"]
+    except (ValueError, KeyError):
+        pass
+    return None
+
+
+def sync():
+    try:
+        import torch
+        if torch.cuda.is_available():
+            torch.cuda.synchronize()
+    except ImportError:
+        pass
+
+
+def run_gpu(pm, w, prec, steps, warmup, keep_state=False):
+    n = w.n
+    pm.pm_set_precision(prec)
+    pm.pm_init(w.N, n, n, n, w.h, w.dt, w.sigma_a, w.sigma_s, w.q)
+    try:
+        for i in range(w.V):
+            pm.pm_write(i, w.moment(i))
+        pm.pm_step(warmup)
+        pm.pm_sync()
+        sync()
+        pm.pm_timing(1)
+        t0 = time.perf_counter()
+        pm.pm_step(steps)
+        pm.pm_sync()
+        sync()
+        t1 = time.perf_counter()
+        times = pm.pm_sweep_times()
+        pm.pm_timing(0)
+        state = None
+        if keep_state:
+            state = [pm.pm_read(i) for i in range(w.V)]
+        maxabs, nonfinite = pm.pm_check()
+        return t1 - t0, times, state, (maxabs, nonfinite)
+    finally:
+        pm.pm_finalize()
+
+
+def roofline(N, ncell, esz, times):
+    n_odd, ms_odd = times["odd"]
+    per_launch = ms_odd / max(n_odd, 1) / 1e3
+    byts = sweep_bytes(N, ncell, esz, 1)
+    achieved = byts / per_launch / 1e9
+    return {"kernel": "sweep_odd", "bound": "hbm", "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "bytes_per_launch": byts, "ms_per_launch": round(per_launch * 1e3, 4)}
+
+
+def cpu_baseline(w, steps):
+    from oracle import c_oracle
+    c_oracle.build(force=False)
+    u0 = w.initial()
+    threads = c_oracle.threads()
+    t0 = time.perf_counter()
+    c_oracle.run(w.N, w.shape, w.h, w.dt, w.sigma_a, w.sigma_s, w.q, u0, steps)
+    dt = time.perf_counter() - t0
+    return {"value": round(w.n ** 3 * w.V * steps / dt / 1e9, 5), "unit": "GDoF-updates/s",
+            "cores": threads, "kind": "oracle",
+            "sample": "%d of %d steps of %s (P%d, %d^3), plain C/OpenMP FP64, %.1f s"
+                      % (steps, w.nsteps, w.name, w.N, w.n, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="p39_smooth")
+    ap.add_argument("--cpu-steps", type=int, default=8)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only (the step is measured on one "
+              "MI355X; multi-GPU sharding is a design note, not an implementation).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import paper_2004_02833_amd as pm
+    import workloads
+
+    w = workloads.RECIPES[args.workload]()
+    ncell = w.n ** 3
+    V = w.V
+    say = lambda *a: print(*a, file=sys.stderr, flush=True)
+
+    say("bench: %s P%d %d^3, fp64, %d warmup + %d steps" % (w.name, w.N, w.n, args.warmup, args.steps))
+    t64, times64, s64, chk64 = run_gpu(pm, w, pm.PM_FP64, args.steps, args.warmup,
+                                       keep_state=not args.no_fp32)
+    value = ncell * V * args.steps / t64 / 1e9
+    roof = roofline(w.N, ncell, 8, times64)
+    roof["traffic"] = measured_traffic("sweep_odd", w.name, "f64")
+
+    fp32 = None
+    if not args.no_fp32:
+        say("bench: fp32")
+        t32, times32, s32, chk32 = run_gpu(pm, w, pm.PM_FP32, args.steps, args.warmup,
+                                           keep_state=True)
+        num = max(float(np.abs(a - b).max()) for a, b in zip(s32, s64))
+        den = max(float(np.abs(b).max()) for b in s64)
+        r32 = roofline(w.N, ncell, 4, times32)
+        r32["traffic"] = measured_traffic("sweep_odd", w.name, "f32")
+        fp32 = {"value": round(ncell * V * args.steps / t32 / 1e9, 3),
+                "ms_per_step": round(t32 / args.steps * 1e3, 4),
+                "rel_err_vs_fp64_gpu": num / den, "roofline": r32}
+        del s32, s64
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        say("bench: cpu oracle sample (%d steps)" % args.cpu_steps)
+        cpu = cpu_baseline(w, args.cpu_steps)
+
+    out = {
+        "metric": "GDoF-updates/s (cell x moment per step) P39 3D; % HBM peak; FP32 vs FP64 error",
+        "value": round(value, 3),
+        "unit": "GDoF-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(t64 / args.steps * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "%s: P%d (%d moments), %d^3 periodic cells, dx=1/%d, dt=dx/2, "
+                               "smooth random medium, 3 Gaussian pulses + N(0,1e-3) moments"
+                               % (w.name, w.N, V, w.n, w.n),
+                   "cells": ncell, "moments": V, "seed": w.seed},
+        "roofline": roof,
+        "fp32": fp32,
+        "cpu_baseline": cpu,
+        "state_check": {"max_abs": chk64[0], "nonfinite": chk64[1]},
+        "sweep_ms": {"odd": times64["odd"], "even": times64["even"]},
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

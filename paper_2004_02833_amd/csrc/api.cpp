@@ -1,0 +1,615 @@
+// C ABI of libpm: context management, validation and the step driver.
+//
+// A time step is the Strang composition of eq. (6): the odd-grid half step,
+// the even-grid full step and the odd-grid half step, each one sweep launch
+// on the bound stream (paper Sec. 2.1 and Sec. 3.2, where a step is the
+// sweeps S^o, S^e, S^o).  The gradient pass walks the recorded steps
+// backwards from device checkpoints (the paper has no derivatives; this is
+// the transpose of the discrete step).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/pm.h"
+#include "kernels.h"
+#include "pm_internal.h"
+
+namespace {
+
+std::string g_err = "no error";
+int g_pending_prec = PM_FP64;
+hipStream_t g_bound = nullptr;  // caller's stream (nullptr: own stream)
+
+int fail(int code, const std::string& msg) {
+    g_err = msg;
+    return code;
+}
+
+#define HIPCHK(x)                                                                   \
+    do {                                                                            \
+        hipError_t e_ = (x);                                                        \
+        if (e_ != hipSuccess)                                                       \
+            return fail(e_ == hipErrorOutOfMemory ? PM_ENOMEM : PM_EDEVICE,         \
+                        std::string(#x) + ": " + hipGetErrorString(e_));            \
+    } while (0)
+
+size_t elem_size(int prec) { return prec == PM_FP64 ? 8 : prec == PM_FP32 ? 4 : 2; }
+
+struct Ctx {
+    bool live = false;
+    int N = 0, V = 0, nx = 0, ny = 0, nz = 0;
+    long long ncell = 0;
+    double dx = 0, dt = 0;
+    int prec = PM_FP64;
+    size_t esz = 8;
+    pm::GridDesc g{};
+    pm::Layout L;
+    void* u = nullptr;
+    double* tab = nullptr;
+    double* sig = nullptr;  // sigma_a, sigma_s (device copies)
+    void* sched_mem = nullptr;
+    pm::Schedule sched[2]{};  // [0] even targets, [1] odd targets
+    double* plane64 = nullptr;
+    double* red = nullptr;
+    unsigned long long* redc = nullptr;
+    int npart = 256;
+    hipStream_t own = nullptr;
+    int cfl_warn = 0;
+    int ck = 0;
+    long long rec_steps = 0;
+    std::vector<void*> ckpts;
+    bool timing = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[2];
+    long long dev_bytes = 0;
+    long long base_bytes = 0;
+
+    size_t state_bytes() const { return (size_t)V * (size_t)g.pstride * esz; }
+    hipStream_t stream() const { return g_bound ? g_bound : own; }
+    void* plane(void* base, int slot) const {
+        return (char*)base + (size_t)slot * (size_t)g.pstride * esz;
+    }
+};
+
+Ctx C;
+
+template <class P>
+int dmalloc(P** p, size_t bytes, const char* what) {
+    void* q = nullptr;
+    hipError_t e = hipMalloc(&q, bytes ? bytes : 1);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(e == hipErrorOutOfMemory ? PM_ENOMEM : PM_EDEVICE,
+                    std::string("hipMalloc(") + what + ", " + std::to_string(bytes) +
+                        " bytes): " + hipGetErrorString(e));
+    }
+    C.dev_bytes += (long long)bytes;
+    *p = (P*)q;
+    return PM_OK;
+}
+
+void dfree(void* p) {
+    if (p) (void)hipFree(p);
+}
+
+void drop_recording() {
+    for (void* p : C.ckpts) dfree(p);
+    C.ckpts.clear();
+    C.rec_steps = 0;
+}
+
+void drop_events() {
+    for (auto& v : C.ev)
+        for (auto& pr : v) {
+            (void)hipEventDestroy(pr.first);
+            (void)hipEventDestroy(pr.second);
+        }
+    C.ev[0].clear();
+    C.ev[1].clear();
+}
+
+void release() {
+    drop_recording();
+    drop_events();
+    dfree(C.u);
+    dfree(C.tab);
+    dfree(C.sig);
+    dfree(C.sched_mem);
+    dfree(C.plane64);
+    dfree(C.red);
+    dfree(C.redc);
+    if (C.own) (void)hipStreamDestroy(C.own);
+    C = Ctx();
+}
+
+bool finite_nonneg(const double* a, long long n, const char* name, std::string& msg) {
+    for (long long i = 0; i < n; ++i)
+        if (!std::isfinite(a[i]) || a[i] < 0.0) {
+            msg = std::string(name) + "[" + std::to_string(i) + "] is negative or not finite";
+            return false;
+        }
+    return true;
+}
+
+// Plane stride: a multiple of 64 elements, padded so that consecutive planes
+// do not sit at power-of-two distances.
+long long plane_stride(long long ncell) {
+    long long s = (ncell + 63) / 64 * 64;
+    if ((s & (s - 1)) == 0 && s >= 4096) s += 64;
+    return s;
+}
+
+int build_schedules() {
+    const pm::Layout& L = C.L;
+    std::vector<pm::FluxEntry> fe = pm::flux_entries(C.N);
+    std::vector<std::vector<const pm::FluxEntry*>> by_row(C.V);
+    for (const auto& e : fe) by_row[e.row].push_back(&e);
+    std::vector<pm::SweepRow> rows[2];
+    std::vector<pm::SweepEnt> ents[2];
+    for (int slot = 0; slot < C.V; ++slot) {
+        const int i = L.moment_of[slot];
+        int l, m;
+        pm::moment_lm(i, l, m);
+        const int bits = pm::grid_bits(l, m);
+        const int par = __builtin_popcount(bits) & 1;
+        pm::SweepRow r;
+        r.slot = slot;
+        r.tab = (i == 0) ? pm::kTabMom0 : 2 * L.order_of[i];
+        r.begin = (int)ents[par].size();
+        for (const pm::FluxEntry* e : by_row[i]) {
+            const int stag = (bits >> e->dir) & 1;  // target staggered in d: forward difference
+            pm::SweepEnt s;
+            s.slot = L.slot_of[e->col];
+            s.nb = 2 * e->dir + (stag ? 0 : 1);
+            s.K = (stag ? 1.0 : -1.0) * e->val / C.dx;
+            ents[par].push_back(s);
+        }
+        r.end = (int)ents[par].size();
+        rows[par].push_back(r);
+    }
+    size_t bytes = 0;
+    size_t off_rows[2], off_ents[2];
+    for (int p = 0; p < 2; ++p) {
+        off_rows[p] = bytes;
+        bytes += (rows[p].size() * sizeof(pm::SweepRow) + 15) / 16 * 16;
+        off_ents[p] = bytes;
+        bytes += (ents[p].size() * sizeof(pm::SweepEnt) + 15) / 16 * 16;
+    }
+    int rc = dmalloc(&C.sched_mem, bytes, "schedule");
+    if (rc) return rc;
+    for (int p = 0; p < 2; ++p) {
+        char* base = (char*)C.sched_mem;
+        if (!rows[p].empty())
+            HIPCHK(hipMemcpy(base + off_rows[p], rows[p].data(), rows[p].size() * sizeof(pm::SweepRow),
+                             hipMemcpyHostToDevice));
+        if (!ents[p].empty())
+            HIPCHK(hipMemcpy(base + off_ents[p], ents[p].data(), ents[p].size() * sizeof(pm::SweepEnt),
+                             hipMemcpyHostToDevice));
+        C.sched[p].rows = (const pm::SweepRow*)(base + off_rows[p]);
+        C.sched[p].nrows = (int)rows[p].size();
+        C.sched[p].ents = (const pm::SweepEnt*)(base + off_ents[p]);
+    }
+    return PM_OK;
+}
+
+int sweep(void* u, int parity) {
+    if (C.sched[parity].nrows == 0) return PM_OK;
+    hipEvent_t a = nullptr, b = nullptr;
+    if (C.timing) {
+        HIPCHK(hipEventCreate(&a));
+        HIPCHK(hipEventCreate(&b));
+        HIPCHK(hipEventRecord(a, C.stream()));
+    }
+    HIPCHK(pm::launch_sweep(C.prec, u, C.tab, C.sched[parity], C.g, C.stream()));
+    if (C.timing) {
+        HIPCHK(hipEventRecord(b, C.stream()));
+        C.ev[parity].push_back({a, b});
+    }
+    return PM_OK;
+}
+
+int full_step(void* u) {
+    int rc;
+    if ((rc = sweep(u, 1))) return rc;
+    if ((rc = sweep(u, 0))) return rc;
+    return sweep(u, 1);
+}
+
+int check_moment(int moment) {
+    if (!C.live) return fail(PM_ESTATE, "no context: call pm_init first");
+    if (moment < 0 || moment >= C.V)
+        return fail(PM_EINVAL, "moment " + std::to_string(moment) + " out of range [0, " +
+                                   std::to_string(C.V) + ")");
+    return PM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pm_set_precision(int p) {
+    if (p != PM_FP64 && p != PM_FP32 && p != PM_BF16)
+        return fail(PM_EINVAL, "unknown precision " + std::to_string(p));
+    g_pending_prec = p;
+    return PM_OK;
+}
+
+int pm_init(int N, int nx, int ny, int nz, double dx, double dt, const double* sigma_a,
+            const double* sigma_s, const double* q) {
+    if (N < 0 || N > PM_N_MAX) return fail(PM_EINVAL, "N must be in [0, 63]");
+    if (nx < 1 || ny < 1 || nz < 1) return fail(PM_EINVAL, "grid sizes must be >= 1");
+    const long long ncell = (long long)nx * ny * nz;
+    if (ncell >= (1LL << 31)) return fail(PM_EINVAL, "more than 2^31 - 1 cells");
+    if (!(dx > 0.0) || !std::isfinite(dx)) return fail(PM_EINVAL, "dx must be positive and finite");
+    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(PM_EINVAL, "dt must be positive and finite");
+    if (!sigma_a || !sigma_s) return fail(PM_EINVAL, "sigma_a and sigma_s are required");
+    std::string msg;
+    if (!finite_nonneg(sigma_a, ncell, "sigma_a", msg) || !finite_nonneg(sigma_s, ncell, "sigma_s", msg))
+        return fail(PM_EINVAL, msg);
+    if (q)
+        for (long long i = 0; i < ncell; ++i)
+            if (!std::isfinite(q[i])) return fail(PM_EINVAL, "q[" + std::to_string(i) + "] not finite");
+
+    release();
+    C.N = N;
+    C.V = (N + 1) * (N + 1);
+    C.nx = nx;
+    C.ny = ny;
+    C.nz = nz;
+    C.ncell = ncell;
+    C.dx = dx;
+    C.dt = dt;
+    C.prec = g_pending_prec;
+    C.esz = elem_size(C.prec);
+    C.g.nx = nx;
+    C.g.ny = ny;
+    C.g.nz = nz;
+    C.g.ncell = ncell;
+    C.g.pstride = plane_stride(ncell);
+    C.L = pm::make_layout(N);
+    const double lim = N > 0 ? dx / (std::sqrt(3.0) * pm::lambda_max(N)) : INFINITY;
+    C.cfl_warn = dt > lim ? 1 : 0;
+
+    int rc;
+    hipError_t e = hipStreamCreate(&C.own);
+    if (e != hipSuccess) {
+        C.own = nullptr;
+        release();
+        return fail(PM_EDEVICE, std::string("hipStreamCreate: ") + hipGetErrorString(e));
+    }
+#define TRY(x)            \
+    do {                  \
+        rc = (x);         \
+        if (rc) {         \
+            release();    \
+            return rc;    \
+        }                 \
+    } while (0)
+    {
+        size_t fr = 0, tot = 0;
+        hipError_t me = hipMemGetInfo(&fr, &tot);
+        const size_t need = C.state_bytes() + sizeof(double) * (pm::kTabRows + 3) * (size_t)ncell;
+        if (me != hipSuccess) {
+            release();
+            return fail(PM_EDEVICE, std::string("hipMemGetInfo: ") + hipGetErrorString(me));
+        }
+        if (need > fr) {
+            release();
+            return fail(PM_ENOMEM, "context needs " + std::to_string(need) + " bytes, " +
+                                       std::to_string(fr) + " free on the device");
+        }
+    }
+    TRY(dmalloc(&C.u, C.state_bytes(), "state"));
+    TRY(dmalloc(&C.tab, sizeof(double) * pm::kTabRows * (size_t)ncell, "tables"));
+    TRY(dmalloc(&C.sig, sizeof(double) * 2 * (size_t)ncell, "sigma"));
+    TRY(dmalloc(&C.plane64, sizeof(double) * (size_t)ncell, "plane"));
+    TRY(dmalloc(&C.red, sizeof(double) * (C.npart + 1), "reduction"));
+    TRY(dmalloc(&C.redc, sizeof(unsigned long long) * (C.npart + 1), "reduction"));
+    TRY(build_schedules());
+    hipStream_t s = C.stream();
+    auto dev = [&](hipError_t err, const char* what) -> int {
+        if (err == hipSuccess) return PM_OK;
+        return fail(PM_EDEVICE, std::string(what) + ": " + hipGetErrorString(err));
+    };
+    TRY(dev(hipMemcpyAsync(C.sig, sigma_a, sizeof(double) * ncell, hipMemcpyHostToDevice, s), "copy sigma_a"));
+    TRY(dev(hipMemcpyAsync(C.sig + ncell, sigma_s, sizeof(double) * ncell, hipMemcpyHostToDevice, s), "copy sigma_s"));
+    if (q) TRY(dev(hipMemcpyAsync(C.plane64, q, sizeof(double) * ncell, hipMemcpyHostToDevice, s), "copy q"));
+    TRY(dev(pm::launch_tables(C.sig, C.sig + ncell, q ? C.plane64 : nullptr, C.tab, C.g, dt, s), "tables"));
+    TRY(dev(pm::launch_fill_zero(C.u, (long long)C.state_bytes(), s), "zero state"));
+    TRY(dev(hipStreamSynchronize(s), "sync"));
+#undef TRY
+    C.base_bytes = C.dev_bytes;
+    C.live = true;
+    return PM_OK;
+}
+
+int pm_write(int moment, const double* src) {
+    int rc = check_moment(moment);
+    if (rc) return rc;
+    if (!src) return fail(PM_EINVAL, "src is NULL");
+    hipStream_t s = C.stream();
+    const int slot = C.L.slot_of[moment];
+    if (C.prec == PM_FP64) {
+        HIPCHK(hipMemcpyAsync(C.plane(C.u, slot), src, sizeof(double) * C.ncell, hipMemcpyHostToDevice, s));
+    } else {
+        HIPCHK(hipMemcpyAsync(C.plane64, src, sizeof(double) * C.ncell, hipMemcpyHostToDevice, s));
+        HIPCHK(pm::launch_from_f64(C.prec, C.plane64, C.plane(C.u, slot), C.ncell, s));
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    drop_recording();
+    return PM_OK;
+}
+
+int pm_write_dev(int moment, const void* dsrc) {
+    int rc = check_moment(moment);
+    if (rc) return rc;
+    if (!dsrc) return fail(PM_EINVAL, "src is NULL");
+    const int slot = C.L.slot_of[moment];
+    HIPCHK(pm::launch_from_f64(C.prec, (const double*)dsrc, C.plane(C.u, slot), C.ncell, C.stream()));
+    drop_recording();
+    return PM_OK;
+}
+
+int pm_step(int nsteps) {
+    if (!C.live) return fail(PM_ESTATE, "no context: call pm_init first");
+    if (nsteps < 0) return fail(PM_EINVAL, "nsteps < 0");
+    int rc;
+    for (int s = 0; s < nsteps; ++s) {
+        if (C.ck > 0 && C.rec_steps % C.ck == 0) {
+            size_t fr = 0, tot = 0;
+            HIPCHK(hipMemGetInfo(&fr, &tot));
+            if (C.state_bytes() > fr) return fail(PM_ENOMEM, "no device memory for a checkpoint");
+            void* p = nullptr;
+            if ((rc = dmalloc(&p, C.state_bytes(), "checkpoint"))) return rc;
+            C.ckpts.push_back(p);
+            HIPCHK(hipMemcpyAsync(p, C.u, C.state_bytes(), hipMemcpyDeviceToDevice, C.stream()));
+        }
+        if ((rc = full_step(C.u))) return rc;
+        if (C.ck > 0) ++C.rec_steps;
+    }
+    return PM_OK;
+}
+
+int pm_read(int moment, double* dst) {
+    int rc = check_moment(moment);
+    if (rc) return rc;
+    if (!dst) return fail(PM_EINVAL, "dst is NULL");
+    hipStream_t s = C.stream();
+    const int slot = C.L.slot_of[moment];
+    if (C.prec == PM_FP64) {
+        HIPCHK(hipMemcpyAsync(dst, C.plane(C.u, slot), sizeof(double) * C.ncell, hipMemcpyDeviceToHost, s));
+    } else {
+        HIPCHK(pm::launch_to_f64(C.prec, C.plane(C.u, slot), C.plane64, C.ncell, s));
+        HIPCHK(hipMemcpyAsync(dst, C.plane64, sizeof(double) * C.ncell, hipMemcpyDeviceToHost, s));
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    return PM_OK;
+}
+
+int pm_read_dev(int moment, void* ddst) {
+    int rc = check_moment(moment);
+    if (rc) return rc;
+    if (!ddst) return fail(PM_EINVAL, "dst is NULL");
+    const int slot = C.L.slot_of[moment];
+    HIPCHK(pm::launch_to_f64(C.prec, C.plane(C.u, slot), (double*)ddst, C.ncell, C.stream()));
+    return PM_OK;
+}
+
+int pm_set_checkpoint(int k) {
+    if (k < 0) return fail(PM_EINVAL, "checkpoint interval < 0");
+    if (!C.live) return fail(PM_ESTATE, "no context: call pm_init first");
+    if (k > 0 && C.prec == PM_BF16)
+        return fail(PM_EINVAL, "gradients are not supported for bfloat16 storage");
+    drop_recording();
+    C.ck = k;
+    return PM_OK;
+}
+
+int pm_grad(const double* dL_du0, double* dsa, double* dss) {
+    if (!C.live) return fail(PM_ESTATE, "no context: call pm_init first");
+    if (C.ck <= 0) return fail(PM_ESTATE, "no gradient recording: call pm_set_checkpoint(k > 0) before pm_step");
+    if (!dL_du0) return fail(PM_EINVAL, "dL_du0 is NULL");
+    hipStream_t s = C.stream();
+    const size_t SB = C.state_bytes();
+    const long long n = C.ncell;
+    const long long T = C.rec_steps;
+    const int ck = C.ck;
+    void *lam = nullptr, *w = nullptr, *ua = nullptr, *ub = nullptr, *seg = nullptr;
+    double *grad = nullptr, *outg = nullptr;
+    const long long before = C.dev_bytes;
+    const bool timing = C.timing;
+    auto cleanup = [&]() {
+        dfree(lam); dfree(w); dfree(ua); dfree(ub); dfree(seg); dfree(grad); dfree(outg);
+        C.dev_bytes = before;
+        C.timing = timing;
+    };
+    int rc;
+#define TRYG(x)           \
+    do {                  \
+        rc = (x);         \
+        if (rc) {         \
+            cleanup();    \
+            return rc;    \
+        }                 \
+    } while (0)
+#define HIPG(x)                                                                        \
+    do {                                                                               \
+        hipError_t e_ = (x);                                                           \
+        if (e_ != hipSuccess) {                                                        \
+            cleanup();                                                                 \
+            return fail(PM_EDEVICE, std::string(#x) + ": " + hipGetErrorString(e_));   \
+        }                                                                              \
+    } while (0)
+    const int segs = T > 0 ? ck : 1;
+    {
+        size_t fr = 0, tot = 0;
+        HIPCHK(hipMemGetInfo(&fr, &tot));
+        const size_t need = SB * (size_t)(4 + segs) + sizeof(double) * (pm::kGradRows + 2) * (size_t)n;
+        if (need > fr)
+            return fail(PM_ENOMEM, "gradient pass needs " + std::to_string(need) + " bytes, " +
+                                       std::to_string(fr) + " free on the device");
+    }
+    TRYG(dmalloc(&lam, SB, "adjoint state"));
+    TRYG(dmalloc(&w, SB, "adjoint work"));
+    TRYG(dmalloc(&ua, SB, "recompute a"));
+    TRYG(dmalloc(&ub, SB, "recompute b"));
+    TRYG(dmalloc(&seg, SB * (size_t)segs, "segment states"));
+    TRYG(dmalloc(&grad, sizeof(double) * pm::kGradRows * (size_t)n, "gradient accumulators"));
+    TRYG(dmalloc(&outg, sizeof(double) * 2 * (size_t)n, "gradient output"));
+    HIPG(pm::launch_fill_zero(lam, (long long)SB, s));
+    HIPG(pm::launch_fill_zero(w, (long long)SB, s));
+    HIPG(pm::launch_fill_zero(grad, (long long)(sizeof(double) * pm::kGradRows * n), s));
+    HIPG(hipMemcpyAsync(C.plane64, dL_du0, sizeof(double) * n, hipMemcpyHostToDevice, s));
+    HIPG(pm::launch_from_f64(C.prec, C.plane64, C.plane(lam, C.L.slot_of[0]), n, s));
+    C.timing = false;
+    const long long nseg = (T + ck - 1) / ck;
+    for (long long gseg = nseg - 1; gseg >= 0; --gseg) {
+        const long long s0 = gseg * ck, s1 = std::min<long long>(s0 + ck, T);
+        char* sb = (char*)seg;
+        HIPG(hipMemcpyAsync(sb, C.ckpts[gseg], SB, hipMemcpyDeviceToDevice, s));
+        for (long long k = s0 + 1; k < s1; ++k) {
+            void* dst = sb + (size_t)(k - s0) * SB;
+            HIPG(hipMemcpyAsync(dst, sb + (size_t)(k - s0 - 1) * SB, SB, hipMemcpyDeviceToDevice, s));
+            TRYG(full_step(dst));
+        }
+        for (long long k = s1 - 1; k >= s0; --k) {
+            void* un = sb + (size_t)(k - s0) * SB;
+            HIPG(hipMemcpyAsync(ua, un, SB, hipMemcpyDeviceToDevice, s));
+            TRYG(sweep(ua, 1));
+            HIPG(hipMemcpyAsync(ub, ua, SB, hipMemcpyDeviceToDevice, s));
+            TRYG(sweep(ub, 0));
+            const void* olds[3] = {ub, ua, un};
+            const int pars[3] = {1, 0, 1};
+            for (int j = 0; j < 3; ++j) {
+                const int p = pars[j];
+                HIPG(pm::launch_adj_targets(C.prec, olds[j], lam, w, grad, C.tab, C.sched[p], C.g, s));
+                HIPG(pm::launch_adj_duals(C.prec, lam, w, C.sched[1 - p], C.g, s));
+            }
+        }
+    }
+    HIPG(pm::launch_grad_final(grad, C.tab, C.sig, C.sig + n, outg, outg + n, C.g, C.dt, s));
+    if (dsa) HIPG(hipMemcpyAsync(dsa, outg, sizeof(double) * n, hipMemcpyDeviceToHost, s));
+    if (dss) HIPG(hipMemcpyAsync(dss, outg + n, sizeof(double) * n, hipMemcpyDeviceToHost, s));
+    HIPG(hipStreamSynchronize(s));
+    cleanup();
+#undef TRYG
+#undef HIPG
+    return PM_OK;
+}
+
+int pm_total(double* out) {
+    if (!C.live) return fail(PM_ESTATE, "no context: call pm_init first");
+    if (!out) return fail(PM_EINVAL, "out is NULL");
+    hipStream_t s = C.stream();
+    HIPCHK(pm::launch_sum(C.prec, C.plane(C.u, C.L.slot_of[0]), C.ncell, C.red, C.npart,
+                          C.red + C.npart, s));
+    HIPCHK(hipMemcpyAsync(out, C.red + C.npart, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return PM_OK;
+}
+
+int pm_check(double* max_abs, long long* n_nonfinite) {
+    if (!C.live) return fail(PM_ESTATE, "no context: call pm_init first");
+    hipStream_t s = C.stream();
+    HIPCHK(pm::launch_check(C.prec, C.u, C.V, C.g, C.red, C.redc, C.npart, C.red + C.npart,
+                            C.redc + C.npart, s));
+    double m = 0;
+    unsigned long long k = 0;
+    HIPCHK(hipMemcpyAsync(&m, C.red + C.npart, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(&k, C.redc + C.npart, sizeof(k), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (max_abs) *max_abs = m;
+    if (n_nonfinite) *n_nonfinite = (long long)k;
+    if (k) return fail(PM_ENONFINITE, std::to_string(k) + " non-finite values in the state");
+    return PM_OK;
+}
+
+int pm_bind_stream(void* stream) {
+    g_bound = (hipStream_t)stream;
+    return PM_OK;
+}
+
+int pm_sync(void) {
+    if (!C.live) return fail(PM_ESTATE, "no context: call pm_init first");
+    HIPCHK(hipStreamSynchronize(C.stream()));
+    return PM_OK;
+}
+
+int pm_cfl_warning(void) { return C.live ? C.cfl_warn : 0; }
+
+int pm_timing(int on) {
+    if (!C.live) return fail(PM_ESTATE, "no context: call pm_init first");
+    HIPCHK(hipStreamSynchronize(C.stream()));
+    drop_events();
+    C.timing = on != 0;
+    return PM_OK;
+}
+
+int pm_sweep_times(int* n_odd, double* ms_odd, int* n_even, double* ms_even) {
+    if (!C.live) return fail(PM_ESTATE, "no context: call pm_init first");
+    HIPCHK(hipStreamSynchronize(C.stream()));
+    double t[2] = {0, 0};
+    for (int p = 0; p < 2; ++p)
+        for (auto& pr : C.ev[p]) {
+            float ms = 0;
+            HIPCHK(hipEventElapsedTime(&ms, pr.first, pr.second));
+            t[p] += ms;
+        }
+    if (n_odd) *n_odd = (int)C.ev[1].size();
+    if (ms_odd) *ms_odd = t[1];
+    if (n_even) *n_even = (int)C.ev[0].size();
+    if (ms_even) *ms_even = t[0];
+    return PM_OK;
+}
+
+void pm_finalize(void) {
+    if (C.live || C.u || C.own) {
+        if (C.own || g_bound) (void)hipStreamSynchronize(C.stream());
+        release();
+    }
+}
+
+const char* pm_last_error(void) { return g_err.c_str(); }
+
+int pm_flux_nnz(int N) {
+    if (N < 0 || N > PM_N_MAX) return fail(PM_EINVAL, "N must be in [0, 63]");
+    return (int)pm::flux_entries(N).size();
+}
+
+int pm_flux_entries(int N, int* row, int* col, int* dir, double* value, int cap) {
+    if (N < 0 || N > PM_N_MAX) return fail(PM_EINVAL, "N must be in [0, 63]");
+    if (cap < 0) return fail(PM_EINVAL, "cap < 0");
+    std::vector<pm::FluxEntry> e = pm::flux_entries(N);
+    int k = 0;
+    for (; k < (int)e.size() && k < cap; ++k) {
+        if (row) row[k] = e[k].row;
+        if (col) col[k] = e[k].col;
+        if (dir) dir[k] = e[k].dir;
+        if (value) value[k] = e[k].val;
+    }
+    return k;
+}
+
+int pm_moment_grid(int N, int moment) {
+    if (N < 0 || N > PM_N_MAX) return fail(PM_EINVAL, "N must be in [0, 63]");
+    if (moment < 0 || moment >= (N + 1) * (N + 1)) return fail(PM_EINVAL, "moment out of range");
+    int l, m;
+    pm::moment_lm(moment, l, m);
+    return pm::grid_bits(l, m);
+}
+
+int pm_moment_slot(int N, int moment) {
+    if (N < 0 || N > PM_N_MAX) return fail(PM_EINVAL, "N must be in [0, 63]");
+    if (moment < 0 || moment >= (N + 1) * (N + 1)) return fail(PM_EINVAL, "moment out of range");
+    return pm::make_layout(N).slot_of[moment];
+}
+
+long long pm_device_bytes(void) {
+    return C.live ? C.base_bytes + (long long)C.ckpts.size() * (long long)C.state_bytes() : 0;
+}
+
+}  // extern "C"

@@ -1,0 +1,80 @@
+// Device-side data structures and launchers of libpm (internal).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace pm {
+
+enum Prec { kF64 = 0, kF32 = 1, kBF16 = 2 };
+
+// Table rows (float64 planes of ncell values): alpha/beta of grid g in rows
+// 2g and 2g+1 (g in storage order), moment 0 in rows 16/17, q in row 18.
+constexpr int kTabRows = 19;
+constexpr int kTabMom0 = 16;
+constexpr int kTabQ = 18;
+// Gradient accumulators: rows 2s (d/d alpha) and 2s+1 (d/d beta), s = 0..8
+// (grid g -> s = g, moment 0 -> s = 8).
+constexpr int kGradRows = 18;
+
+struct GridDesc {
+    int nx, ny, nz;
+    long long ncell;
+    long long pstride;  // elements between consecutive moment planes
+};
+
+// One target moment of a sweep: storage slot, alpha table row, and its
+// range of entries in the entry list.
+struct SweepRow {
+    int slot;
+    int tab;
+    int begin;
+    int end;
+};
+
+// One coupling: source slot, neighbour code (0:+x 1:-x 2:+y 3:-y 4:+z 5:-z)
+// and K = s * M_d[i, j] / dx with s = +1 for a forward and -1 for a
+// backward difference, so that M_d D_d u_j = K (u_j[c + s e_d] - u_j[c]).
+struct SweepEnt {
+    int slot;
+    int nb;
+    double K;
+};
+
+struct Schedule {
+    const SweepRow* rows;
+    int nrows;
+    const SweepEnt* ents;
+};
+
+hipError_t launch_tables(const double* sa, const double* ss, const double* q, double* tab,
+                         GridDesc g, double dt, hipStream_t st);
+
+hipError_t launch_sweep(int prec, void* u, const double* tab, Schedule s, GridDesc g,
+                        hipStream_t st);
+
+hipError_t launch_to_f64(int prec, const void* src_plane, double* dst, long long n,
+                         hipStream_t st);
+hipError_t launch_from_f64(int prec, const double* src, void* dst_plane, long long n,
+                           hipStream_t st);
+
+// sum of moment-0 plane into *out (device double), two-pass deterministic.
+hipError_t launch_sum(int prec, const void* plane, long long n, double* partial, int npart,
+                      double* out, hipStream_t st);
+// max |u| and non-finite count over nplanes planes.
+hipError_t launch_check(int prec, const void* u, int nplanes, GridDesc g, double* pmax,
+                        unsigned long long* pcount, int npart, double* out_max,
+                        unsigned long long* out_count, hipStream_t st);
+
+// Adjoint of one substep (targets = schedule `tgt`, duals = schedule `dual`).
+hipError_t launch_adj_targets(int prec, const void* uold, void* lam, void* w, double* grad,
+                              const double* tab, Schedule tgt, GridDesc g, hipStream_t st);
+hipError_t launch_adj_duals(int prec, void* lam, const void* w, Schedule dual, GridDesc g,
+                            hipStream_t st);
+hipError_t launch_grad_final(const double* grad, const double* tab, const double* sa,
+                             const double* ss, double* dsa, double* dss, GridDesc g, double dt,
+                             hipStream_t st);
+
+hipError_t launch_fill_zero(void* p, long long bytes, hipStream_t st);
+
+}  // namespace pm

@@ -1,0 +1,74 @@
+"""GPU adjoint: pm_grad (transposed steps from checkpoints) against the FP64
+oracle adjoint, and against central finite differences of the GPU forward."""
+import numpy as np
+import pytest
+
+import paper_2004_02833_amd as pm
+from oracle import adjoint as adj
+from oracle import c_oracle
+from oracle import stepper as st
+
+from gpu_util import gpu_init, relerr, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def oracle_built():
+    c_oracle.build(force=False)
+    yield
+    pm.pm_finalize()
+
+
+def gpu_grad(N, shape, h, dt, sa, ss, q, u0, nsteps, ck, target, prec=0):
+    gpu_init(N, shape, h, dt, sa, ss, q, prec)
+    try:
+        for i in range((N + 1) ** 2):
+            pm.pm_write(i, u0[i])
+        pm.pm_set_checkpoint(ck)
+        pm.pm_step(nsteps)
+        u0T = pm.pm_read(0)
+        dsa, dss = pm.pm_grad(u0T - target)
+        u0T_after = pm.pm_read(0)
+        assert np.array_equal(u0T, u0T_after), "pm_grad must leave the forward state unchanged"
+        L = 0.5 * float(np.sum((u0T - target) ** 2))
+        return L, dsa, dss
+    finally:
+        pm.pm_finalize()
+
+
+@pytest.mark.parametrize("N,shape,nsteps,ck", [(3, (4, 5, 6), 7, 3), (1, (3, 3, 3), 4, 1),
+                                               (2, (1, 2, 9), 5, 5), (3, (2, 3, 70), 3, 2)])
+def test_grad_matches_numpy_oracle(N, shape, nsteps, ck):
+    say("case adjoint small", N, shape, nsteps, ck)
+    rng = np.random.default_rng(N * 7 + nsteps)
+    sa = rng.uniform(0, 0.5, shape)
+    ss = rng.uniform(0, 1, shape)
+    q = rng.uniform(0, 1, shape)
+    u = rng.normal(size=((N + 1) ** 2,) + shape)
+    tgt = rng.normal(size=shape)
+    h, dt = 0.2, 0.07
+    L, ga, gs, _ = adj.loss_and_grad(st.Setup(N, shape, h, dt, sa, ss, q), u, nsteps, tgt)
+    L2, ga2, gs2 = gpu_grad(N, shape, h, dt, sa, ss, q, u, nsteps, ck, tgt)
+    assert abs(L - L2) <= 1e-13 * L
+    assert relerr(ga2, ga) <= 1e-12
+    assert relerr(gs2, gs) <= 1e-12
+
+
+def test_grad_p7_reduced_vs_c_oracle():
+    """The gradient workload recipe (P7, blocks of 4^3) at 16^3, 40 steps,
+    checkpoints every 20 steps, against the C oracle adjoint."""
+    import workloads
+    w = workloads.p7_adjoint(n=16, nsteps=40)
+    say("case adjoint p7 16^3")
+    u0 = w.initial()
+    tgt = c_oracle.run(w.N, w.shape, w.h, w.dt, w.extra["perturbed_sigma_a"], w.sigma_s, w.q,
+                       u0, w.nsteps)[0]
+    L, ga, gs = c_oracle.grad(w.N, w.shape, w.h, w.dt, w.sigma_a, w.sigma_s, w.q, u0, w.nsteps,
+                              w.checkpoint, tgt)
+    L2, ga2, gs2 = gpu_grad(w.N, w.shape, w.h, w.dt, w.sigma_a, w.sigma_s, w.q, u0, w.nsteps,
+                            w.checkpoint, tgt)
+    say("p7 16^3 adjoint rel err", relerr(ga2, ga), relerr(gs2, gs))
+    assert abs(L - L2) <= 1e-12 * L
+    assert relerr(ga2, ga) <= 1e-11
+    assert relerr(gs2, gs) <= 1e-11

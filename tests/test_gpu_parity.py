@@ -1,0 +1,217 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle on
+the same seeded inputs.  FP64 must agree to 1e-12 relative (normwise max
+over all moments and cells); FP32 storage to 1e-5; BF16 storage is a probe
+(reported, loose bound)."""
+import numpy as np
+import pytest
+
+import paper_2004_02833_amd as pm
+import workloads
+from oracle import c_oracle, dense
+from oracle import stepper as st
+
+from gpu_util import gpu_init, gpu_run, relerr, say
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-12
+FP32_TOL = 1e-5
+
+
+@pytest.fixture(scope="module", autouse=True)
+def oracle_built():
+    c_oracle.build(force=False)
+    yield
+    pm.pm_finalize()
+
+
+def rand_problem(N, shape, seed, q=True):
+    rng = np.random.default_rng(seed)
+    sa = rng.uniform(0, 0.5, shape)
+    ss = rng.uniform(0, 1, shape)
+    qq = rng.uniform(0, 1, shape) if q else None
+    u = rng.normal(size=((N + 1) ** 2,) + tuple(shape))
+    return sa, ss, qq, u
+
+
+def test_p3_pulse_full_fp64():
+    """P3, 32^3, dx = 1/32, dt = dx/2, 64 steps: all 16 moments."""
+    w = workloads.p3_pulse()
+    say("case p3_pulse fp64", w.shape, w.nsteps)
+    u0 = w.initial()
+    got = gpu_run(w.N, w.shape, w.h, w.dt, w.sigma_a, w.sigma_s, w.q, u0, w.nsteps)
+    ref = c_oracle.run(w.N, w.shape, w.h, w.dt, w.sigma_a, w.sigma_s, w.q, u0, w.nsteps)
+    e = relerr(got, ref)
+    say("p3_pulse fp64 rel err", e)
+    assert e <= FP64_TOL
+
+
+@pytest.mark.parametrize("N,shape", [(0, (3, 4, 5)), (1, (4, 4, 4)), (3, (2, 3, 4)), (2, (1, 1, 7)),
+                                     (3, (5, 1, 1)), (2, (1, 6, 1)), (7, (3, 5, 7)), (3, (5, 7, 9)),
+                                     (4, (1, 1, 1)), (3, (3, 2, 67))])
+def test_small_and_ragged_fp64(N, shape):
+    """Tiny, degenerate (n_d = 1, a single cell) and ragged grids whose cell
+    counts are not multiples of the 64-lane wave or the 256-thread block."""
+    say("case small", N, shape)
+    sa, ss, q, u = rand_problem(N, shape, 100 + N)
+    h, dt = 0.2, 0.07
+    got = gpu_run(N, shape, h, dt, sa, ss, q, u, 5)
+    ref = st.run(st.Setup(N, shape, h, dt, sa, ss, q), u, 5)
+    assert relerr(got, ref) <= 1e-13
+
+
+def test_p7_lattice_reduced_fp64_fp32():
+    """The 7^3 absorber lattice recipe at 40^3 (blocks of 5-6 cells), 30 steps."""
+    w = workloads.p7_lattice(n=40, nsteps=30)
+    say("case p7_lattice 40^3")
+    u0 = w.initial()
+    ref = c_oracle.run(w.N, w.shape, w.h, w.dt, w.sigma_a, w.sigma_s, w.q, u0, w.nsteps)
+    got = gpu_run(w.N, w.shape, w.h, w.dt, w.sigma_a, w.sigma_s, w.q, u0, w.nsteps)
+    e64 = relerr(got, ref)
+    got32 = gpu_run(w.N, w.shape, w.h, w.dt, w.sigma_a, w.sigma_s, w.q, u0, w.nsteps,
+                    prec=pm.PM_FP32)
+    e32 = relerr(got32, ref)
+    say("p7_lattice 40^3 rel err fp64 %.3e fp32 %.3e" % (e64, e32))
+    assert e64 <= FP64_TOL
+    assert e32 <= FP32_TOL
+
+
+def test_p39_full_grid_fp64_fp32_bf16():
+    """P39 on the full 64^3 grid of the smooth-medium workload, 2 steps (the
+    oracle needs ~10 s per step there).  FP64 to 1e-12, FP32 to 1e-5; BF16
+    storage is reported with a loose bound."""
+    w = workloads.p39_smooth()
+    ns = 2
+    say("case p39_smooth 64^3, %d steps" % ns)
+    u0 = w.initial()
+    ref = c_oracle.run(w.N, w.shape, w.h, w.dt, w.sigma_a, w.sigma_s, w.q, u0, ns)
+    errs = {}
+    for prec, name in ((pm.PM_FP64, "fp64"), (pm.PM_FP32, "fp32"), (pm.PM_BF16, "bf16")):
+        say("  gpu", name)
+        got = gpu_run(w.N, w.shape, w.h, w.dt, w.sigma_a, w.sigma_s, w.q, u0, ns, prec=prec)
+        errs[name] = relerr(got, ref)
+        del got
+    say("p39_smooth rel err", errs)
+    assert errs["fp64"] <= FP64_TOL
+    assert errs["fp32"] <= FP32_TOL
+    assert errs["bf16"] <= 1e-2
+
+
+def test_conservation_on_gpu():
+    """sigma_a = 0, q = 0: pm_total (float64 sum of u_0) stays constant."""
+    shape = (16, 12, 20)
+    rng = np.random.default_rng(7)
+    ss = rng.uniform(0, 2, shape)
+    gpu_init(7, shape, 1 / 16, 0.5 / 16, np.zeros(shape), ss)
+    try:
+        pm.pm_write(0, rng.uniform(0, 1, shape))
+        for i in range(1, 64):
+            pm.pm_write(i, rng.normal(0, 0.1, shape))
+        t0 = pm.pm_total()
+        for _ in range(10):
+            pm.pm_step(5)
+            assert abs(pm.pm_total() - t0) <= 1e-13 * abs(t0)
+    finally:
+        pm.pm_finalize()
+
+
+def test_exact_decay_on_gpu():
+    """Homogeneous state and medium: u_0 = q/sa + (u_0(0) - q/sa) e^{-sa t},
+    u_{l>=1} = u(0) e^{-(sa + ss) t} at every step boundary."""
+    shape = (4, 4, 8)
+    sa, ss, qv = 0.7, 1.3, 0.4
+    gpu_init(3, shape, 0.2, 0.05, np.full(shape, sa), np.full(shape, ss), np.full(shape, qv))
+    try:
+        for i in range(16):
+            pm.pm_write(i, np.full(shape, 1.0 + i))
+        for k in range(1, 11):
+            pm.pm_step(1)
+            t = k * 0.05
+            assert np.abs(pm.pm_read(0) - (qv / sa + (1 - qv / sa) * np.exp(-sa * t))).max() < 1e-14
+            for i in (1, 7, 15):
+                assert np.abs(pm.pm_read(i) - (1.0 + i) * np.exp(-(sa + ss) * t)).max() < 1e-13
+    finally:
+        pm.pm_finalize()
+
+
+def test_fourier_mode_on_gpu():
+    N, shape, h = 3, (8, 8, 8), 1 / 8
+    dt = 0.45 * h
+    sa = np.full(shape, 0.2)
+    ss = np.full(shape, 0.5)
+    o = st.Setup(N, shape, h, dt, sa, ss).o
+    k = 2 * np.pi * np.array([1.0, -2.0, 3.0])
+    rng = np.random.default_rng(3)
+    uh = rng.normal(size=16) + 1j * rng.normal(size=16)
+    ph = np.empty((16,) + shape, dtype=complex)
+    for i in range(16):
+        x, y, z = dense.staggered_positions(shape, (h, h, h), o[i])
+        ph[i] = np.exp(1j * (k[0] * x + k[1] * y + k[2] * z))
+    G = dense.fourier_symbol(N, k, (h, h, h), dt, 0.2, 0.7)
+    want = ((np.linalg.matrix_power(G, 6) @ uh)[:, None, None, None] * ph).real
+    got = gpu_run(N, shape, h, dt, sa, ss, None, (uh[:, None, None, None] * ph).real, 6)
+    assert relerr(got, want) < 1e-13
+
+
+def test_translation_bitwise_on_gpu():
+    """Shifting data and medium by a cell shifts the result bit for bit
+    (every cell runs the same instruction sequence; periodic wrap)."""
+    N, shape = 3, (6, 5, 70)
+    sa, ss, q, u = rand_problem(N, shape, 9)
+    a = gpu_run(N, shape, 0.1, 0.04, sa, ss, q, u, 4)
+    for ax in (-1, -2, -3):
+        r = lambda v: np.roll(v, 1, axis=ax)
+        b = gpu_run(N, shape, 0.1, 0.04, r(sa), r(ss), r(q), r(u), 4)
+        assert np.array_equal(r(a), b)
+
+
+def test_deterministic_reruns():
+    N, shape = 7, (8, 8, 8)
+    sa, ss, q, u = rand_problem(N, shape, 10)
+    a = gpu_run(N, shape, 0.1, 0.04, sa, ss, q, u, 3)
+    b = gpu_run(N, shape, 0.1, 0.04, sa, ss, q, u, 3)
+    assert np.array_equal(a, b)
+
+
+def test_errors_and_recovery_on_gpu():
+    shape = (4, 4, 4)
+    z = np.zeros(shape)
+    gpu_init(3, shape, 0.25, 0.1, z, z)
+    try:
+        assert pm.pm_cfl_warning() == 0
+        with pytest.raises(pm.PmError) as e:
+            pm.pm_write(16, z)
+        assert e.value.code == pm.PM_EINVAL
+        with pytest.raises(pm.PmError) as e:
+            pm.pm_read(-1)
+        assert e.value.code == pm.PM_EINVAL
+        with pytest.raises(pm.PmError) as e:
+            pm.pm_step(-1)
+        assert e.value.code == pm.PM_EINVAL
+        with pytest.raises(pm.PmError) as e:
+            pm.pm_grad(z)
+        assert e.value.code == pm.PM_ESTATE
+        bad = np.zeros(shape)
+        bad[1, 2, 3] = np.nan
+        pm.pm_write(5, bad)
+        m, k = pm.pm_check()
+        assert k == 1
+        assert pm.lib().pm_check(None, None) == pm.PM_ENONFINITE
+    finally:
+        pm.pm_finalize()
+    # dt above the stability limit: warning only
+    gpu_init(3, shape, 0.25, 0.25 * 0.7, z, z)
+    assert pm.pm_cfl_warning() == 1
+    pm.pm_finalize()
+    # an allocation far beyond 288 GB fails cleanly, and the library recovers
+    n = 300
+    big = np.zeros(n * n * n)
+    with pytest.raises(pm.PmError) as e:
+        pm.pm_init(63, n, n, n, 1.0 / n, 0.5 / n, big, big)
+    assert e.value.code == pm.PM_ENOMEM
+    del big
+    gpu_init(1, shape, 0.25, 0.1, z, z)
+    pm.pm_write(0, np.ones(shape))
+    pm.pm_step(2)
+    assert abs(pm.pm_total() - 64.0) < 1e-12
+    pm.pm_finalize()

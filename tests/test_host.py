@@ -1,0 +1,113 @@
+"""Host logic of the HIP library, runnable without a GPU: the library loads,
+exports every symbol of include/pm.h, and its closed-form setup (flux
+matrices, grid assignment, storage order) equals the oracle's quadrature and
+reflection parities.  Argument validation that happens before any device
+call is checked here too."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2004_02833_amd as pm
+from oracle import basis
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_symbols():
+    txt = open(os.path.join(ROOT, "include", "pm.h")).read()
+    return sorted(set(re.findall(r"^\s*(?:int|void|const char\*|long long)\s+(pm_\w+)\s*\(", txt, re.M)))
+
+
+def test_library_exports_header():
+    L = pm.lib()
+    syms = header_symbols()
+    assert len(syms) >= 20
+    for s in syms:
+        assert hasattr(L, s), s
+    assert sorted(pm.EXPORTED) == syms
+
+
+@pytest.mark.parametrize("N", [0, 1, 2, 3, 7, 12, 20, 39])
+def test_flux_closed_form_equals_quadrature(N):
+    r, c, d, v = pm.pm_flux_entries(N)
+    V = (N + 1) ** 2
+    Q = basis.flux_matrices(N)
+    G = [np.zeros((V, V)) for _ in range(3)]
+    for a, b, k, x in zip(r, c, d, v):
+        assert G[k][a, b] == 0.0, "duplicate entry"
+        G[k][a, b] = x
+    for k in range(3):
+        assert np.array_equal(G[k] != 0, Q[k] != 0)
+        assert np.abs(G[k] - Q[k]).max() <= 8 * np.finfo(float).eps
+        assert np.array_equal(G[k], G[k].T)
+
+
+@pytest.mark.parametrize("N", [1, 3, 7, 39])
+def test_grid_assignment_equals_reflection_parity(N):
+    o = basis.reflection_parities(N)
+    for i in range(basis.n_moments(N)):
+        bits = pm.pm_moment_grid(N, i)
+        assert (bits & 1, (bits >> 1) & 1, (bits >> 2) & 1) == tuple(o[i])
+
+
+def test_storage_order_grouped_by_grid():
+    order = ["G111", "G221", "G212", "G122", "G211", "G121", "G112", "G222"]
+    for N in (3, 7, 39):
+        fam = basis.families(N)
+        slots = [pm.pm_moment_slot(N, i) for i in range(len(fam))]
+        assert sorted(slots) == list(range(len(fam)))
+        by_slot = [None] * len(fam)
+        for i, s in enumerate(slots):
+            by_slot[s] = (order.index(fam[i]), i)
+        assert by_slot == sorted(by_slot)
+
+
+def test_validation_before_device():
+    ok = np.zeros(8)
+    cases = [
+        (-1, 2, 2, 2, 0.5, 0.1, ok, ok),
+        (64, 2, 2, 2, 0.5, 0.1, ok, ok),
+        (3, 0, 2, 2, 0.5, 0.1, ok, ok),
+        (3, 2, 2, 2, 0.0, 0.1, ok, ok),
+        (3, 2, 2, 2, 0.5, -0.1, ok, ok),
+        (3, 2, 2, 2, 0.5, float("nan"), ok, ok),
+        (3, 2, 2, 2, 0.5, 0.1, -np.ones(8), ok),
+        (3, 2, 2, 2, 0.5, 0.1, ok, np.full(8, np.inf)),
+    ]
+    for args in cases:
+        with pytest.raises(pm.PmError) as e:
+            pm.pm_init(*args)
+        assert e.value.code == pm.PM_EINVAL
+    with pytest.raises(pm.PmError) as e:
+        pm.pm_init(3, 2, 2, 2, 0.5, 0.1, ok, ok, np.full(8, np.nan))
+    assert e.value.code == pm.PM_EINVAL
+    with pytest.raises(pm.PmError) as e:
+        pm.pm_set_precision(7)
+    assert e.value.code == pm.PM_EINVAL
+    for bad in (-1, 64):
+        with pytest.raises(pm.PmError):
+            pm.pm_flux_nnz(bad)
+        with pytest.raises(pm.PmError):
+            pm.pm_moment_grid(bad, 0)
+    with pytest.raises(pm.PmError):
+        pm.pm_moment_grid(3, 16)
+
+
+def test_calls_without_context():
+    pm.pm_finalize()
+    assert pm.lib().pm_step(1) == pm.PM_ESTATE
+    assert pm.lib().pm_read(0, None) == pm.PM_ESTATE
+    assert pm.lib().pm_grad(None, None, None) == pm.PM_ESTATE
+    assert pm.lib().pm_set_checkpoint(1) == pm.PM_ESTATE
+    assert pm.lib().pm_set_checkpoint(-1) == pm.PM_EINVAL
+    assert pm.lib().pm_sync() == pm.PM_ESTATE
+    assert pm.pm_cfl_warning() == 0
+    assert pm.pm_device_bytes() == 0
+    pm.pm_finalize()
+
+
+def test_paper_nnz_counts_from_library():
+    for N, total in ((3, 70), (7, 438), (39, 14902)):
+        assert pm.pm_flux_nnz(N) == total
