@@ -12,6 +12,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <unordered_map>
 #include <utility>
 #include <vector>
 
@@ -54,6 +55,8 @@ struct Ctx {
     double* sig = nullptr;  // sigma_a, sigma_s (device copies)
     void* sched_mem = nullptr;
     pm::Schedule sched[2]{};  // [0] even targets, [1] odd targets
+    void* win_mem = nullptr;  // window sweep streams (both parities)
+    pm::WinArgs win[2]{};
     double* plane64 = nullptr;
     double* red = nullptr;
     unsigned long long* redc = nullptr;
@@ -119,6 +122,7 @@ void release() {
     dfree(C.tab);
     dfree(C.sig);
     dfree(C.sched_mem);
+    dfree(C.win_mem);
     dfree(C.plane64);
     dfree(C.red);
     dfree(C.redc);
@@ -196,6 +200,116 @@ int build_schedules() {
     return PM_OK;
 }
 
+// Streams of the window sweep (layout documented in kernels.h).  Every
+// nonzero flux entry with a target of the sweep's parity must land in exactly
+// one coefficient slot; the count is checked.
+int build_window_tables() {
+    const pm::Layout& L = C.L;
+    const int N = C.N, V = C.V, MU1 = N + 2;
+    const int K = pm::win_depth(C.prec);
+    std::unordered_map<long long, double> flux;
+    long long nnz_par[2] = {0, 0};
+    for (const pm::FluxEntry& e : pm::flux_entries(N)) {
+        flux[((long long)e.row * V + e.col) * 3 + e.dir] = e.val;
+        int l, m;
+        pm::moment_lm(e.row, l, m);
+        ++nnz_par[l & 1];
+    }
+    auto exists = [&](int l, int mu, int ty) {
+        return l >= 0 && l <= N && mu >= 0 && mu <= l && !(ty == 1 && mu == 0);
+    };
+    auto idx = [](int l, int mu, int ty) { return l * l + l + (ty == 0 ? mu : -mu); };
+    struct Host {
+        std::vector<int2> src, tgt;
+        std::vector<double> coef;
+    } H[2];
+    for (int p = 0; p < 2; ++p) {
+        const int npass = N >= p ? (N - p) / (2 * K) + 1 : 0;
+        C.win[p].N = N;
+        C.win[p].parity = p;
+        C.win[p].K = K;
+        C.win[p].npass = npass;
+        Host& h = H[p];
+        h.src.assign((size_t)npass * MU1 * (K + 1) * 2, make_int2(-1, 0));
+        h.tgt.assign((size_t)npass * MU1 * K * 2, make_int2(-1, 0));
+        h.coef.assign((size_t)npass * MU1 * (K + 1) * 20, 0.0);
+        long long used = 0;
+        for (int pass = 0; pass < npass; ++pass) {
+            const int L0 = p + 2 * K * pass;
+            for (int mu = 0; mu < MU1; ++mu) {
+                for (int b = 0; b <= K; ++b)
+                    for (int ty = 0; ty < 2; ++ty) {
+                        const int ls = L0 - 1 + 2 * b;
+                        if (!exists(ls, mu, ty)) continue;
+                        const int j = idx(ls, mu, ty);
+                        const int bits = pm::grid_bits(ls, ty == 0 ? mu : -mu);
+                        h.src[((size_t)(pass * MU1 + mu) * (K + 1) + b) * 2 + ty] = make_int2(L.slot_of[j], bits);
+                        for (int side = 0; side < 2; ++side) {
+                            const int t = side == 0 ? b : b - 1;
+                            if (t < 0 || t >= K) continue;
+                            const int lt = L0 + 2 * t;
+                            // (target column, target type, direction) of the five roles
+                            const int tmu[5] = {mu - 1, mu - 1, mu, mu + 1, mu + 1};
+                            const int tty[5] = {ty, 1 - ty, ty, ty, 1 - ty};
+                            const int dir[5] = {0, 1, 2, 0, 1};
+                            for (int r = 0; r < 5; ++r) {
+                                if (!exists(lt, tmu[r], tty[r])) continue;
+                                const int i = idx(lt, tmu[r], tty[r]);
+                                auto it = flux.find(((long long)i * V + j) * 3 + dir[r]);
+                                if (it == flux.end()) continue;
+                                const double sgn = ((bits >> dir[r]) & 1) ? -1.0 : 1.0;
+                                h.coef[((((size_t)(pass * MU1 + mu) * (K + 1) + b) * 2 + ty) * 2 + side) * 5 + r] =
+                                    sgn * it->second / C.dx;
+                                ++used;
+                            }
+                        }
+                    }
+                for (int t = 0; t < K; ++t)
+                    for (int ty = 0; ty < 2; ++ty) {
+                        const int lt = L0 + 2 * t;
+                        if (!exists(lt, mu, ty)) continue;
+                        const int i = idx(lt, mu, ty);
+                        const int row = i == 0 ? pm::kTabMom0 : 2 * L.order_of[i];
+                        h.tgt[((size_t)(pass * MU1 + mu) * K + t) * 2 + ty] = make_int2(L.slot_of[i], row);
+                    }
+            }
+        }
+        if (used != nnz_par[p])
+            return fail(PM_EINVAL, "internal: window streams cover " + std::to_string(used) + " of " +
+                                       std::to_string(nnz_par[p]) + " couplings");
+    }
+    const bool f64 = C.prec == PM_FP64;
+    const size_t es = f64 ? sizeof(double) : sizeof(float);
+    auto up = [](size_t x) { return (x + 255) / 256 * 256; };
+    size_t total = 0, off[2][3];
+    for (int p = 0; p < 2; ++p) {
+        off[p][0] = total; total += up(H[p].src.size() * sizeof(int2));
+        off[p][1] = total; total += up(H[p].tgt.size() * sizeof(int2));
+        off[p][2] = total; total += up(H[p].coef.size() * es);
+    }
+    int rc = dmalloc(&C.win_mem, total, "window streams");
+    if (rc) return rc;
+    char* base = (char*)C.win_mem;
+    for (int p = 0; p < 2; ++p) {
+        if (!H[p].src.empty())
+            HIPCHK(hipMemcpy(base + off[p][0], H[p].src.data(), H[p].src.size() * sizeof(int2), hipMemcpyHostToDevice));
+        if (!H[p].tgt.empty())
+            HIPCHK(hipMemcpy(base + off[p][1], H[p].tgt.data(), H[p].tgt.size() * sizeof(int2), hipMemcpyHostToDevice));
+        if (!H[p].coef.empty()) {
+            if (f64) {
+                HIPCHK(hipMemcpy(base + off[p][2], H[p].coef.data(), H[p].coef.size() * es, hipMemcpyHostToDevice));
+            } else {
+                std::vector<float> c32(H[p].coef.begin(), H[p].coef.end());
+                HIPCHK(hipMemcpy(base + off[p][2], c32.data(), c32.size() * es, hipMemcpyHostToDevice));
+            }
+        }
+        C.win[p].src = (const int2*)(base + off[p][0]);
+        C.win[p].tgt = (const int2*)(base + off[p][1]);
+        C.win[p].coef = base + off[p][2];
+    }
+    return PM_OK;
+}
+
 int sweep(void* u, int parity) {
     if (C.sched[parity].nrows == 0) return PM_OK;
     hipEvent_t a = nullptr, b = nullptr;
@@ -204,7 +318,7 @@ int sweep(void* u, int parity) {
         HIPCHK(hipEventCreate(&b));
         HIPCHK(hipEventRecord(a, C.stream()));
     }
-    HIPCHK(pm::launch_sweep(C.prec, u, C.tab, C.sched[parity], C.g, C.stream()));
+    HIPCHK(pm::launch_sweep_win(C.prec, u, C.tab, C.win[parity], C.g, C.stream()));
     if (C.timing) {
         HIPCHK(hipEventRecord(b, C.stream()));
         C.ev[parity].push_back({a, b});
@@ -310,6 +424,7 @@ int pm_init(int N, int nx, int ny, int nz, double dx, double dt, const double* s
     TRY(dmalloc(&C.red, sizeof(double) * (C.npart + 1), "reduction"));
     TRY(dmalloc(&C.redc, sizeof(unsigned long long) * (C.npart + 1), "reduction"));
     TRY(build_schedules());
+    TRY(build_window_tables());
     hipStream_t s = C.stream();
     auto dev = [&](hipError_t err, const char* what) -> int {
         if (err == hipSuccess) return PM_OK;

@@ -47,11 +47,42 @@ struct Schedule {
     const SweepEnt* ents;
 };
 
+// Window sweep (see kernels.hip).  A sweep of one parity is split into
+// passes of K target degrees; pass p, source column mu (0 <= mu <= N + 1)
+// is described by host-built streams, in the order the kernel consumes them:
+//   src[((p * MU1 + mu) * (K + 1) + b) * 2 + ty] = {slot or -1, parity bits}
+//       source degree L0 - 1 + 2b, m = +mu (ty 0, cos) or -mu (ty 1, sin);
+//   tgt[((p * MU1 + mu) * K + t) * 2 + ty] = {slot or -1, alpha table row}
+//       target degree L0 + 2t, m = +-mu;
+//   coef[(((p * MU1 + mu) * (K + 1) + b) * 2 + ty) * 2 + side) * 5 + r]
+//       coupling of that source (column mu) to the targets of degree
+//       ls + 1 (side 0) or ls - 1 (side 1):
+//       r = 0: x to column mu-1 (same type)   1: y to column mu-1 (other type)
+//           2: z to column mu (same m)        3: x to column mu+1   4: y to column mu+1
+//       value K = s * M_d[i, j] / dx (s = +1 if the source is unstaggered in
+//       d, else -1), zero where the target does not exist.
+// with MU1 = N + 2 and L0 = parity + 2 K p.
+struct WinArgs {
+    int N;
+    int parity;   // parity (l mod 2) of the target moments
+    int K;        // target degrees per pass
+    int npass;
+    const int2* src;
+    const int2* tgt;
+    const void* coef;  // values of the accumulation type
+};
+
+// Target degrees per pass used for a storage precision.
+int win_depth(int prec);
+
 hipError_t launch_tables(const double* sa, const double* ss, const double* q, double* tab,
                          GridDesc g, double dt, hipStream_t st);
 
 hipError_t launch_sweep(int prec, void* u, const double* tab, Schedule s, GridDesc g,
                         hipStream_t st);
+
+hipError_t launch_sweep_win(int prec, void* u, const double* tab, WinArgs a, GridDesc g,
+                            hipStream_t st);
 
 hipError_t launch_to_f64(int prec, const void* src_plane, double* dst, long long n,
                          hipStream_t st);

@@ -12,6 +12,13 @@
 
 #include "kernels.h"
 
+#ifndef PM_WIN_K64
+#define PM_WIN_K64 2
+#endif
+#ifndef PM_WIN_K32
+#define PM_WIN_K32 3
+#endif
+
 namespace pm {
 
 // ---------------------------------------------------------------- storage --
@@ -43,6 +50,22 @@ __device__ __forceinline__ void st(bf16s* p, double v) {
     else
         r = (uint16_t)((x + 0x7fffu + ((x >> 16) & 1u)) >> 16);
     p->b = r;
+}
+
+// Streaming (non-temporal) access for values that are read once and written
+// once per sweep (the target moments): keeps L2 for the source rows that are
+// re-read as neighbours by other waves.
+__device__ __forceinline__ double ld_nt(const double* p) { return __builtin_nontemporal_load(p); }
+__device__ __forceinline__ float ld_nt(const float* p) { return __builtin_nontemporal_load(p); }
+__device__ __forceinline__ float ld_nt(const bf16s* p) {
+    return __uint_as_float((uint32_t)__builtin_nontemporal_load(&p->b) << 16);
+}
+__device__ __forceinline__ void st_nt(double* p, double v) { __builtin_nontemporal_store(v, p); }
+__device__ __forceinline__ void st_nt(float* p, double v) { __builtin_nontemporal_store((float)v, p); }
+__device__ __forceinline__ void st_nt(bf16s* p, double v) {
+    bf16s t;
+    st(&t, v);
+    __builtin_nontemporal_store(t.b, &p->b);
 }
 
 // ---------------------------------------------------------------- indexing --
@@ -198,6 +221,222 @@ hipError_t launch_sweep(int prec, void* u, const double* tab, Schedule s, GridDe
         default:
             hipLaunchKernelGGL(k_sweep_gather<bf16s>, dim3(nb), dim3(B), 0, st, (bf16s*)u, tab, s, g);
     }
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------ window sweep --
+// Same substep as k_sweep_gather, organised so that every source moment is
+// loaded once per pass (with its three one-sided neighbours) and its
+// differences are pushed straight into the partial sums of all its targets.
+//
+// Coupling structure (flux matrices in closed form): target (l, m) reads only
+// degrees l-1 and l+1; M_z keeps m, M_x keeps the cos/sin type and moves |m|
+// by one, M_y swaps the type and moves |m| by one.  A pass takes K target
+// degrees l = L0, L0+2, .., L0+2K-2 (one parity) and the K+1 source degrees
+// L0-1, .., L0+2K-1 between them, and walks the source column mu' = |m|
+// upwards.  A source in column mu' feeds target columns mu'-1 (x, y; this
+// completes them), mu' (z) and mu'+1 (x, y), so three columns of partial sums
+// are live.  A difference of source j in direction d is u_j[c + s e_d] - u_j[c]
+// with s = +1 if j is unstaggered in d and -1 otherwise; the sign and 1/dx
+// are folded into the coefficient.  Each source's four raw values for the
+// next column are requested as soon as its current ones are consumed
+// (one-column software pipeline).
+
+template <class T, class A>
+__device__ __forceinline__ void win_fetch(A (&r)[4], const T* __restrict__ u, int2 d,
+                                          const Nbr& nb, long long ps) {
+    if (d.x >= 0) {
+        const T* p = u + (long long)d.x * ps + nb.c;
+        r[0] = (A)ld(p);
+        r[1] = (A)ld(p + ((d.y & 1) ? nb.off[1] : nb.off[0]));
+        r[2] = (A)ld(p + ((d.y & 2) ? nb.off[3] : nb.off[2]));
+        r[3] = (A)ld(p + ((d.y & 4) ? nb.off[5] : nb.off[4]));
+    } else {
+        r[0] = r[1] = r[2] = r[3] = (A)0;
+    }
+}
+
+// Work decomposition: (tile of 256 cells) x (pass of K target degrees);
+// passes are independent (disjoint targets, read-only sources).  When rows
+// split into 64-cell segments (nx % 64 == 0) a tile is TY x TZ segments, one
+// wave per segment, so that most one-sided y/z neighbour rows are loaded by a
+// sibling wave of the same workgroup; otherwise a tile is 256 consecutive
+// cells.  Workgroups are dispatched round-robin over the 8 XCDs (id mod 8),
+// so the id is remapped to give every XCD a contiguous range of tiles (x
+// segment fastest, then y, then z): neighbour tiles then run at about the
+// same time on the same XCD and share its L2.  Within an XCD the most
+// expensive passes (highest degrees) go first.
+constexpr int kXcds = 8;
+
+struct TileMap {
+    int seg;       // 64-cell segments per row (0: linear 256-cell tiles)
+    int ty, tz;    // segments per tile in y and z (ty * tz == 4)
+    int nty, ntz;  // tiles per direction
+};
+
+__device__ __forceinline__ long long tile_cell(const TileMap& m, long long tile, int tid,
+                                               const GridDesc& g, bool& live) {
+    if (m.seg == 0) {
+        const long long c = tile * 256 + tid;
+        live = c < g.ncell;
+        return c;
+    }
+    const long long xs = tile % m.seg;
+    const long long r = tile / m.seg;
+    const int yt = (int)(r % m.nty);
+    const int zt = (int)(r / m.nty);
+    const int w = tid >> 6;
+    const int y = yt * m.ty + (w % m.ty);
+    const int z = zt * m.tz + (w / m.ty);
+    live = y < g.ny && z < g.nz;
+    return (long long)(xs * 64 + (tid & 63)) + (long long)g.nx * ((long long)y + (long long)g.ny * z);
+}
+
+template <class T, int K>
+__global__ void __launch_bounds__(256) k_sweep_win(T* __restrict__ u,
+                                                   const double* __restrict__ tab,
+                                                   const int2* __restrict__ src,
+                                                   const int2* __restrict__ tgt,
+                                                   const typename Acc<T>::type* __restrict__ coef,
+                                                   int N, int parity, int npass, int per_xcd,
+                                                   long long ntile, TileMap tm, GridDesc g) {
+    using A = typename Acc<T>::type;
+    const int xcd = blockIdx.x % kXcds;
+    const int j = blockIdx.x / kXcds;
+    const long long tile = (long long)xcd * per_xcd + (j % per_xcd);
+    const int pass = npass - 1 - j / per_xcd;
+    if (pass < 0 || tile >= ntile) return;
+    bool live;
+    const long long c0 = tile_cell(tm, tile, threadIdx.x, g, live);
+    const long long c = live ? c0 : g.ncell - 1;
+    const Nbr nb = neighbours(c, g);
+    const long long ps = g.pstride;
+    const int gbase = parity ? 4 : 0;  // grids of the target parity in storage order
+    double al[4], be[4];
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+        al[f] = tab[(long long)(2 * (gbase + f)) * g.ncell + c];
+        be[f] = tab[(long long)(2 * (gbase + f) + 1) * g.ncell + c];
+    }
+    double al0 = 1.0, be0 = 0.0, q0 = 0.0;
+    if (parity == 0) {
+        al0 = tab[(long long)kTabMom0 * g.ncell + c];
+        be0 = tab[(long long)(kTabMom0 + 1) * g.ncell + c];
+        q0 = tab[(long long)kTabQ * g.ncell + c];
+    }
+    const int MU1 = N + 2;
+    const int L0 = parity + 2 * K * pass;
+    const int mumax = min(N, L0 + 2 * (K - 1));  // largest target |m| in the pass
+    const int2* sd = src + (long long)pass * MU1 * (K + 1) * 2;
+    const int2* td = tgt + (long long)pass * MU1 * K * 2;
+    const A* cf = coef + (long long)pass * MU1 * (K + 1) * 20;
+
+    A R[K + 1][2][4];  // raw values of the current source column
+    A S[3][K][2];      // partial sums: target columns mu-1, mu, mu+1
+#pragma unroll
+    for (int b = 0; b <= K; ++b)
+#pragma unroll
+        for (int ty = 0; ty < 2; ++ty) win_fetch<T, A>(R[b][ty], u, sd[b * 2 + ty], nb, ps);
+#pragma unroll
+    for (int w = 0; w < 3; ++w)
+#pragma unroll
+        for (int t = 0; t < K; ++t) S[w][t][0] = S[w][t][1] = (A)0;
+
+    for (int mu = 0; mu <= mumax + 1; ++mu) {
+        const int2* sdc = sd + mu * (K + 1) * 2;
+        const int2* sdn = sdc + (K + 1) * 2;
+        const A* cfc = cf + (long long)mu * (K + 1) * 20;
+        // push every source of column mu, then request its next column
+#pragma unroll
+        for (int b = 0; b <= K; ++b) {
+#pragma unroll
+            for (int ty = 0; ty < 2; ++ty) {
+                const A dx = R[b][ty][1] - R[b][ty][0];
+                const A dy = R[b][ty][2] - R[b][ty][0];
+                const A dz = R[b][ty][3] - R[b][ty][0];
+                const bool here = sdc[b * 2 + ty].x >= 0;
+                if (mu <= mumax) win_fetch<T, A>(R[b][ty], u, sdn[b * 2 + ty], nb, ps);
+                if (!here) continue;
+#pragma unroll
+                for (int side = 0; side < 2; ++side) {
+                    const int t = side == 0 ? b : b - 1;
+                    if (t < 0 || t >= K) continue;
+                    const A* k = cfc + ((b * 2 + ty) * 2 + side) * 5;
+                    S[0][t][ty] += k[0] * dx;
+                    S[0][t][1 - ty] += k[1] * dy;
+                    S[1][t][ty] += k[2] * dz;
+                    S[2][t][ty] += k[3] * dx;
+                    S[2][t][1 - ty] += k[4] * dy;
+                }
+            }
+        }
+        // column mu-1 is complete: u <- alpha u + beta (q - sum)
+        if (mu >= 1) {
+            const int2* tdc = td + (mu - 1) * K * 2;
+#pragma unroll
+            for (int t = 0; t < K; ++t) {
+#pragma unroll
+                for (int ty = 0; ty < 2; ++ty) {
+                    const int2 d = tdc[t * 2 + ty];
+                    if (d.x < 0) continue;
+                    double alpha, beta, q = 0.0;
+                    if (d.y == kTabMom0) {
+                        alpha = al0;
+                        beta = be0;
+                        q = q0;
+                    } else {
+                        const int f = (d.y >> 1) & 3;
+                        alpha = f == 0 ? al[0] : f == 1 ? al[1] : f == 2 ? al[2] : al[3];
+                        beta = f == 0 ? be[0] : f == 1 ? be[1] : f == 2 ? be[2] : be[3];
+                    }
+                    T* ut = u + (long long)d.x * ps + c;
+                    const double v = alpha * (double)ld_nt(ut) + beta * (q - (double)S[0][t][ty]);
+                    if (live) st_nt(ut, v);
+                }
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < K; ++t)
+#pragma unroll
+            for (int ty = 0; ty < 2; ++ty) {
+                S[0][t][ty] = S[1][t][ty];
+                S[1][t][ty] = S[2][t][ty];
+                S[2][t][ty] = (A)0;
+            }
+    }
+}
+
+int win_depth(int prec) { return prec == kF64 ? PM_WIN_K64 : PM_WIN_K32; }
+
+
+template <class T, int K>
+static void launch_win_t(T* u, const double* tab, WinArgs a, GridDesc g, hipStream_t st) {
+    using A = typename Acc<T>::type;
+    TileMap tm{0, 1, 1, 1, 1};
+    long long ntile = (g.ncell + 255) / 256;
+    if (g.nx % 64 == 0) {
+        tm.seg = g.nx / 64;
+        tm.ty = 1;  // a tile stacks 4 row segments along z
+        tm.tz = 4;
+        tm.nty = (g.ny + tm.ty - 1) / tm.ty;
+        tm.ntz = (g.nz + tm.tz - 1) / tm.tz;
+        ntile = (long long)tm.seg * tm.nty * tm.ntz;
+    }
+    const int per_xcd = (int)((ntile + kXcds - 1) / kXcds);
+    const unsigned nwg = (unsigned)((long long)kXcds * per_xcd * a.npass);
+    hipLaunchKernelGGL((k_sweep_win<T, K>), dim3(nwg), dim3(256), 0, st, u, tab, a.src, a.tgt,
+                       (const A*)a.coef, a.N, a.parity, a.npass, per_xcd, ntile, tm, g);
+}
+
+hipError_t launch_sweep_win(int prec, void* u, const double* tab, WinArgs a, GridDesc g,
+                            hipStream_t st) {
+    if (a.K != win_depth(prec)) return hipErrorInvalidValue;
+    if (prec == kF64)
+        launch_win_t<double, PM_WIN_K64>((double*)u, tab, a, g, st);
+    else if (prec == kF32)
+        launch_win_t<float, PM_WIN_K32>((float*)u, tab, a, g, st);
+    else
+        launch_win_t<bf16s, PM_WIN_K32>((bf16s*)u, tab, a, g, st);
     return hipGetLastError();
 }
 
