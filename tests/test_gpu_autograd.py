@@ -68,7 +68,7 @@ def fd_gradients(w, target, cells, which, hs, prec=0):
     return out
 
 
-@pytest.mark.parametrize("n,nsteps,ncell", [(64, 200, 8)])
+@pytest.mark.parametrize("n,nsteps,ncell", [(64, 200, 16)])
 def test_gradient_workload_vs_finite_differences(n, nsteps, ncell):
     """P7 gradient workload: autograd dL/dsigma_a, dL/dsigma_s against central
     differences on seeded cells; the FD value closest to the adjoint over the
