@@ -79,12 +79,17 @@ def sync():
 
 
 def run_gpu(pm, w, prec, steps, warmup, keep_state=False):
+    import torch
     n = w.n
+    dev = torch.device("cuda", 0)
     pm.pm_set_precision(prec)
+    pm.pm_bind_stream(torch.cuda.current_stream(dev).cuda_stream)
     pm.pm_init(w.N, n, n, n, w.h, w.dt, w.sigma_a, w.sigma_s, w.q)
     try:
         for i in range(w.V):
-            pm.pm_write(i, w.moment(i))
+            plane = w.moment_device(i, dev)
+            pm.pm_write_dev(i, plane.data_ptr())
+            del plane
         pm.pm_step(warmup)
         pm.pm_sync()
         sync()
@@ -103,6 +108,7 @@ def run_gpu(pm, w, prec, steps, warmup, keep_state=False):
         return t1 - t0, times, state, (maxabs, nonfinite)
     finally:
         pm.pm_finalize()
+        pm.pm_bind_stream(0)
 
 
 def copy_ceiling(gib):
@@ -170,6 +176,7 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--bf16", action="store_true", help="also time the BF16-storage probe")
     ap.add_argument("--copy-gib", type=float, default=2.0,
                     help="size of the calibration copy (0: skip)")
     args = ap.parse_args()
@@ -190,7 +197,7 @@ def main():
     copy = copy_ceiling(args.copy_gib) if args.copy_gib > 0 else None
     say("bench: %s P%d %d^3, fp64, %d warmup + %d steps" % (w.name, w.N, w.n, args.warmup, args.steps))
     t64, times64, s64, chk64 = run_gpu(pm, w, pm.PM_FP64, args.steps, args.warmup,
-                                       keep_state=not args.no_fp32)
+                                       keep_state=not args.no_fp32 or args.bf16)
     value = ncell * V * args.steps / t64 / 1e9
     roof = roofline(w.N, ncell, 8, times64)
     roof["traffic"] = measured_traffic("sweep_odd", w.name, "f64")
@@ -208,7 +215,20 @@ def main():
                 "ms_per_step": round(t32 / args.steps * 1e3, 4),
                 "rel_err_vs_fp64_gpu": num / den, "moments_compared": len(s64),
                 "roofline": r32}
-        del s32, s64
+        del s32
+
+    bf16 = None
+    if args.bf16:
+        say("bench: bf16 storage probe")
+        tb, timesb, sb, chkb = run_gpu(pm, w, pm.PM_BF16, args.steps, args.warmup,
+                                       keep_state=s64 is not None)
+        rb = roofline(w.N, ncell, 2, timesb)
+        bf16 = {"value": round(ncell * V * args.steps / tb / 1e9, 3),
+                "ms_per_step": round(tb / args.steps * 1e3, 4), "roofline": rb}
+        if s64 is not None:
+            bf16["rel_err_vs_fp64_gpu"] = (max(float(np.abs(a - b).max()) for a, b in zip(sb, s64))
+                                           / max(float(np.abs(b).max()) for b in s64))
+        del sb
 
     cpu = None
     if not args.no_cpu_baseline and w.n ** 3 * w.V > 1_000_000_000:
@@ -235,6 +255,7 @@ def main():
                    "cells": ncell, "moments": V, "seed": w.seed},
         "roofline": roof,
         "fp32": fp32,
+        "bf16": bf16,
         "cpu_baseline": cpu,
         "copy_ceiling": copy,
         "state_check": {"max_abs": chk64[0], "nonfinite": chk64[1]},

@@ -1,0 +1,89 @@
+"""Full-size parity: the configurations run at their real grid sizes and in
+the launch configuration bench.py times, checked on sampled 8^3 sub-blocks
+against the FP64 oracle run on a periodic window around each block (exact by
+the dependence radius, see test_window_oracle.py)."""
+import numpy as np
+import pytest
+
+import paper_2004_02833_amd as pm
+import workloads
+
+from gpu_util import relerr, say, window_index, window_oracle
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+TOL = {pm.PM_FP64: 1e-12, pm.PM_FP32: 1e-5, pm.PM_BF16: 1e-2}
+NAME = {pm.PM_FP64: "fp64", pm.PM_FP32: "fp32", pm.PM_BF16: "bf16"}
+
+
+def run_blocks(w, prec, nsteps, corners, B, R, want_windows):
+    """Run the library on the full grid; return the sub-blocks after nsteps
+    and (optionally) the initial windows for the oracle."""
+    dev = torch.device("cuda", 0)
+    n = w.n
+    pm.pm_set_precision(prec)
+    pm.pm_bind_stream(torch.cuda.current_stream(dev).cuda_stream)
+    pm.pm_init(w.N, n, n, n, w.h, w.dt, w.sigma_a, w.sigma_s, w.q)
+    wins = None
+    try:
+        idx = [tuple(torch.as_tensor(a, device=dev) for a in window_index(w.shape, c, B, R))
+               for c in corners]
+        if want_windows:
+            wins = [np.empty((w.V, B + 2 * R, B + 2 * R, B + 2 * R)) for _ in corners]
+        for i in range(w.V):
+            plane = w.moment_device(i, dev)
+            pm.pm_write_dev(i, plane.data_ptr())
+            if want_windows:
+                for k, (iz, iy, ix) in enumerate(idx):
+                    wins[k][i] = plane[iz][:, iy][:, :, ix].cpu().numpy()
+            del plane
+        pm.pm_step(nsteps)
+        buf = torch.empty(w.shape, dtype=torch.float64, device=dev)
+        blocks = [np.empty((w.V, B, B, B)) for _ in corners]
+        for i in range(w.V):
+            pm.pm_read_dev(i, buf.data_ptr())
+            for k, c in enumerate(corners):
+                iz, iy, ix = (torch.as_tensor((np.arange(B) + c[d]) % n, device=dev) for d in range(3))
+                blocks[k][i] = buf[iz][:, iy][:, :, ix].cpu().numpy()
+        m, bad = pm.pm_check()
+        assert bad == 0
+        return blocks, wins
+    finally:
+        pm.pm_finalize()
+        pm.pm_bind_stream(0)
+
+
+def check(w, precs, nsteps, corners, B=8):
+    R = 3 * nsteps
+    refs = None
+    errs = {}
+    for prec in precs:
+        say("  %s %s %d^3, %d steps" % (w.name, NAME[prec], w.n, nsteps))
+        blocks, wins = run_blocks(w, prec, nsteps, corners, B, R, refs is None)
+        if refs is None:
+            refs = [window_oracle(w.N, w.shape, w.h, w.dt, w.sigma_a, w.sigma_s, w.q, win, c, B, R,
+                                  nsteps) for win, c in zip(wins, corners)]
+            del wins
+        errs[NAME[prec]] = max(relerr(b, r) for b, r in zip(blocks, refs))
+        assert all(np.abs(r).max() > 0 for r in refs)
+    say("  %s sub-block rel err %s" % (w.name, errs))
+    for prec in precs:
+        assert errs[NAME[prec]] <= TOL[prec], (NAME[prec], errs)
+
+
+def test_p39_large_160_cubed():
+    """P39 at 160^3 (6.6e9 unknowns; 52 GB in FP64, 26 GB in FP32, 13 GB in
+    BF16), the grid whose rows are not multiples of 64 cells."""
+    w = workloads.p39_large()
+    rng = np.random.default_rng(11)
+    corners = [tuple(int(v) for v in rng.integers(0, 160, 3)), (156, 0, 77)]
+    check(w, (pm.PM_FP64, pm.PM_FP32, pm.PM_BF16), 2, corners)
+
+
+def test_p7_lattice_128_cubed():
+    """P7 absorber lattice at 128^3 (two 64-cell segments per row), 8 steps:
+    blocks at the source block and across an absorber boundary."""
+    w = workloads.p7_lattice()
+    corners = [(58, 58, 58), (50, 60, 66)]
+    check(w, (pm.PM_FP64, pm.PM_FP32), 8, corners)
