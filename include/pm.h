@@ -81,12 +81,23 @@ int pm_write(int moment, const double* src);
  * stream).  The caller keeps ownership. */
 int pm_write_dev(int moment, const void* device_src);
 
-/* Advance nsteps >= 0 time steps (eq. (6)): three sweep launches per step,
- * odd half step, even full step, odd half step, queued on the bound stream
- * without host synchronisation.  When a gradient recording is active the
- * state is checkpointed every k steps (pm_set_checkpoint).
+/* Advance nsteps >= 0 time steps (eq. (6)): odd half step, even full step,
+ * odd half step per step (adjacent odd half steps merged, see pm_set_merge),
+ * queued on the bound stream without host synchronisation.  When a gradient
+ * recording is active the state is checkpointed every k steps
+ * (pm_set_checkpoint).
  * Errors: PM_ESTATE, PM_EINVAL, PM_EDEVICE, PM_ENOMEM (checkpoint). */
 int pm_step(int nsteps);
+
+/* Step schedule used by pm_step (default 1).  With 1, the odd half step
+ * that ends a step and the one that starts the next are applied as one odd
+ * substep of length dt: both see the same even moments (eq. (4)) and the odd
+ * moments have no source, so the two exact solutions of eq. (5) compose to
+ * the exact solution over dt.  n steps then take 2n + 1 sweep launches
+ * instead of 3n; states at the end of a pm_step call (and at checkpoints)
+ * are step-boundary states, equal to the three-sweep schedule up to
+ * rounding.  0 runs every step as its three substeps.  PM_EINVAL otherwise. */
+int pm_set_merge(int on);
 
 /* Copy moment `moment` to a host float64 array (synchronises the stream).
  * Moment 0 is the physical output (Sec. 2.1).  Errors: PM_ESTATE, PM_EINVAL. */

@@ -17,7 +17,8 @@ PM_OK, PM_EINVAL, PM_ENOMEM, PM_EDEVICE, PM_ESTATE, PM_ENONFINITE = 0, -1, -2, -
 PM_FP64, PM_FP32, PM_BF16 = 0, 1, 2
 PM_N_MAX = 63
 
-EXPORTED = ("pm_set_precision", "pm_init", "pm_write", "pm_write_dev", "pm_step", "pm_read",
+EXPORTED = ("pm_set_precision", "pm_init", "pm_write", "pm_write_dev", "pm_step", "pm_set_merge",
+            "pm_read",
             "pm_read_dev", "pm_set_checkpoint", "pm_grad", "pm_total", "pm_check",
             "pm_bind_stream", "pm_sync", "pm_cfl_warning", "pm_timing", "pm_sweep_times",
             "pm_finalize", "pm_last_error", "pm_flux_nnz", "pm_flux_entries", "pm_moment_grid",
@@ -52,6 +53,7 @@ def lib():
             "pm_write": ([i32, P(f64)], i32),
             "pm_write_dev": ([i32, vp], i32),
             "pm_step": ([i32], i32),
+            "pm_set_merge": ([i32], i32),
             "pm_read": ([i32, P(f64)], i32),
             "pm_read_dev": ([i32, vp], i32),
             "pm_set_checkpoint": ([i32], i32),
@@ -140,6 +142,10 @@ def pm_write_dev(moment, device_ptr):
 
 def pm_step(nsteps):
     return _check(lib().pm_step(int(nsteps)))
+
+
+def pm_set_merge(on):
+    return _check(lib().pm_set_merge(int(on)))
 
 
 def pm_read(moment, out=None):

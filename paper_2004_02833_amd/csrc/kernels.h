@@ -9,10 +9,14 @@ namespace pm {
 enum Prec { kF64 = 0, kF32 = 1, kBF16 = 2 };
 
 // Table rows (float64 planes of ncell values): alpha/beta of grid g in rows
-// 2g and 2g+1 (g in storage order), moment 0 in rows 16/17, q in row 18.
-constexpr int kTabRows = 19;
+// 2g and 2g+1 (g in storage order; tau = dt/2 on odd grids, dt on even
+// grids), moment 0 in rows 16/17, q in row 18, and alpha/beta of the odd
+// grids for a full step tau = dt in rows 19 + 2f, 20 + 2f (f = g - 4), used
+// when two odd half steps of consecutive steps are merged.
+constexpr int kTabRows = 27;
 constexpr int kTabMom0 = 16;
 constexpr int kTabQ = 18;
+constexpr int kTabOddFull = 19;
 // Gradient accumulators: rows 2s (d/d alpha) and 2s+1 (d/d beta), s = 0..8
 // (grid g -> s = g, moment 0 -> s = 8).
 constexpr int kGradRows = 18;
@@ -81,8 +85,10 @@ hipError_t launch_tables(const double* sa, const double* ss, const double* q, do
 hipError_t launch_sweep(int prec, void* u, const double* tab, Schedule s, GridDesc g,
                         hipStream_t st);
 
-hipError_t launch_sweep_win(int prec, void* u, const double* tab, WinArgs a, GridDesc g,
-                            hipStream_t st);
+// rowbase: table row of alpha for the first target grid of the parity
+// (0 for the even sweep, 8 for an odd half step, kTabOddFull for a full one).
+hipError_t launch_sweep_win(int prec, void* u, const double* tab, int rowbase, WinArgs a,
+                            GridDesc g, hipStream_t st);
 
 hipError_t launch_to_f64(int prec, const void* src_plane, double* dst, long long n,
                          hipStream_t st);

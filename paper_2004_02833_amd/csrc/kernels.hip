@@ -165,6 +165,12 @@ __global__ void k_tables(const double* __restrict__ sa, const double* __restrict
         tab[(long long)(row + 1) * g.ncell + c] = b;
     }
     tab[(long long)kTabQ * g.ncell + c] = q ? q[c] : 0.0;
+    for (int f = 0; f < 4; ++f) {
+        double a, b;
+        decay(cbar_at(sa, ss, c, 4 + f, g), dt, a, b);
+        tab[(long long)(kTabOddFull + 2 * f) * g.ncell + c] = a;
+        tab[(long long)(kTabOddFull + 2 * f + 1) * g.ncell + c] = b;
+    }
 }
 
 hipError_t launch_tables(const double* sa, const double* ss, const double* q, double* tab,
@@ -298,8 +304,9 @@ __global__ void __launch_bounds__(256) k_sweep_win(T* __restrict__ u,
                                                    const int2* __restrict__ src,
                                                    const int2* __restrict__ tgt,
                                                    const typename Acc<T>::type* __restrict__ coef,
-                                                   int N, int parity, int npass, int per_xcd,
-                                                   long long ntile, TileMap tm, GridDesc g) {
+                                                   int rowbase, int N, int parity, int npass,
+                                                   int per_xcd, long long ntile, TileMap tm,
+                                                   GridDesc g) {
     using A = typename Acc<T>::type;
     const int xcd = blockIdx.x % kXcds;
     const int j = blockIdx.x / kXcds;
@@ -311,12 +318,11 @@ __global__ void __launch_bounds__(256) k_sweep_win(T* __restrict__ u,
     const long long c = live ? c0 : g.ncell - 1;
     const Nbr nb = neighbours(c, g);
     const long long ps = g.pstride;
-    const int gbase = parity ? 4 : 0;  // grids of the target parity in storage order
-    double al[4], be[4];
+    double al[4], be[4];  // decay factors of the four target grids
 #pragma unroll
     for (int f = 0; f < 4; ++f) {
-        al[f] = tab[(long long)(2 * (gbase + f)) * g.ncell + c];
-        be[f] = tab[(long long)(2 * (gbase + f) + 1) * g.ncell + c];
+        al[f] = tab[(long long)(rowbase + 2 * f) * g.ncell + c];
+        be[f] = tab[(long long)(rowbase + 2 * f + 1) * g.ncell + c];
     }
     double al0 = 1.0, be0 = 0.0, q0 = 0.0;
     if (parity == 0) {
@@ -410,7 +416,8 @@ int win_depth(int prec) { return prec == kF64 ? PM_WIN_K64 : PM_WIN_K32; }
 
 
 template <class T, int K>
-static void launch_win_t(T* u, const double* tab, WinArgs a, GridDesc g, hipStream_t st) {
+static void launch_win_t(T* u, const double* tab, int rowbase, WinArgs a, GridDesc g,
+                         hipStream_t st) {
     using A = typename Acc<T>::type;
     TileMap tm{0, 1, 1, 1, 1};
     long long ntile = (g.ncell + 255) / 256;
@@ -425,18 +432,18 @@ static void launch_win_t(T* u, const double* tab, WinArgs a, GridDesc g, hipStre
     const int per_xcd = (int)((ntile + kXcds - 1) / kXcds);
     const unsigned nwg = (unsigned)((long long)kXcds * per_xcd * a.npass);
     hipLaunchKernelGGL((k_sweep_win<T, K>), dim3(nwg), dim3(256), 0, st, u, tab, a.src, a.tgt,
-                       (const A*)a.coef, a.N, a.parity, a.npass, per_xcd, ntile, tm, g);
+                       (const A*)a.coef, rowbase, a.N, a.parity, a.npass, per_xcd, ntile, tm, g);
 }
 
-hipError_t launch_sweep_win(int prec, void* u, const double* tab, WinArgs a, GridDesc g,
-                            hipStream_t st) {
+hipError_t launch_sweep_win(int prec, void* u, const double* tab, int rowbase, WinArgs a,
+                            GridDesc g, hipStream_t st) {
     if (a.K != win_depth(prec)) return hipErrorInvalidValue;
     if (prec == kF64)
-        launch_win_t<double, PM_WIN_K64>((double*)u, tab, a, g, st);
+        launch_win_t<double, PM_WIN_K64>((double*)u, tab, rowbase, a, g, st);
     else if (prec == kF32)
-        launch_win_t<float, PM_WIN_K32>((float*)u, tab, a, g, st);
+        launch_win_t<float, PM_WIN_K32>((float*)u, tab, rowbase, a, g, st);
     else
-        launch_win_t<bf16s, PM_WIN_K32>((bf16s*)u, tab, a, g, st);
+        launch_win_t<bf16s, PM_WIN_K32>((bf16s*)u, tab, rowbase, a, g, st);
     return hipGetLastError();
 }
 

@@ -218,3 +218,30 @@ def test_errors_and_recovery_on_gpu():
     pm.pm_step(2)
     assert abs(pm.pm_total() - 64.0) < 1e-12
     pm.pm_finalize()
+
+
+@pytest.mark.parametrize("shape", [(5, 6, 7), (4, 6, 64)])
+def test_merged_schedule(shape):
+    """Merging the adjacent odd half steps (2n+1 sweeps for n steps) gives the
+    three-sweep result up to rounding, also across checkpoint boundaries."""
+    N = 7
+    sa, ss, q, u = rand_problem(N, shape, 21)
+    h, dt, n = 0.15, 0.05, 9
+    ref = st.run(st.Setup(N, shape, h, dt, sa, ss, q), u, n)
+    out = {}
+    for merge, ck in ((0, 0), (1, 0), (1, 4)):
+        pm.pm_set_merge(merge)
+        try:
+            gpu_init(N, shape, h, dt, sa, ss, q)
+            for i in range(64):
+                pm.pm_write(i, u[i])
+            if ck:
+                pm.pm_set_checkpoint(ck)
+            pm.pm_step(n)
+            out[(merge, ck)] = np.stack([pm.pm_read(i) for i in range(64)])
+        finally:
+            pm.pm_finalize()
+            pm.pm_set_merge(1)
+    for k, v in out.items():
+        assert relerr(v, ref) <= 1e-13, k
+    assert relerr(out[(1, 0)], out[(0, 0)]) <= 1e-14

@@ -86,6 +86,11 @@ def test_validation_before_device():
     with pytest.raises(pm.PmError) as e:
         pm.pm_set_precision(7)
     assert e.value.code == pm.PM_EINVAL
+    for bad in (2, -1):
+        with pytest.raises(pm.PmError) as e:
+            pm.pm_set_merge(bad)
+        assert e.value.code == pm.PM_EINVAL
+    pm.pm_set_merge(1)
     for bad in (-1, 64):
         with pytest.raises(pm.PmError):
             pm.pm_flux_nnz(bad)
