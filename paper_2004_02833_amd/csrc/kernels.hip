@@ -12,8 +12,10 @@
 
 #include "kernels.h"
 
+// Target degrees per pass (registers vs re-reading the shared source degree):
+// K = 3 measured best for FP64 and FP32 with the decay factors kept in LDS.
 #ifndef PM_WIN_K64
-#define PM_WIN_K64 2
+#define PM_WIN_K64 3
 #endif
 #ifndef PM_WIN_K32
 #define PM_WIN_K32 3
@@ -275,15 +277,16 @@ __device__ __forceinline__ void win_fetch(A (&r)[4], const T* __restrict__ u, in
 constexpr int kXcds = 8;
 
 struct TileMap {
-    int seg;       // 64-cell segments per row (0: linear 256-cell tiles)
-    int ty, tz;    // segments per tile in y and z (ty * tz == 4)
+    int seg;       // 64-cell segments per row (0: linear tiles of TPB cells)
+    int ty, tz;    // segments per tile in y and z (ty * tz == TPB / 64)
     int nty, ntz;  // tiles per direction
 };
 
+template <int TPB>
 __device__ __forceinline__ long long tile_cell(const TileMap& m, long long tile, int tid,
                                                const GridDesc& g, bool& live) {
     if (m.seg == 0) {
-        const long long c = tile * 256 + tid;
+        const long long c = tile * TPB + tid;
         live = c < g.ncell;
         return c;
     }
@@ -298,8 +301,8 @@ __device__ __forceinline__ long long tile_cell(const TileMap& m, long long tile,
     return (long long)(xs * 64 + (tid & 63)) + (long long)g.nx * ((long long)y + (long long)g.ny * z);
 }
 
-template <class T, int K>
-__global__ void __launch_bounds__(256) k_sweep_win(T* __restrict__ u,
+template <class T, int K, int TPB>
+__global__ void __launch_bounds__(TPB) k_sweep_win(T* __restrict__ u,
                                                    const double* __restrict__ tab,
                                                    const int2* __restrict__ src,
                                                    const int2* __restrict__ tgt,
@@ -314,21 +317,20 @@ __global__ void __launch_bounds__(256) k_sweep_win(T* __restrict__ u,
     const int pass = npass - 1 - j / per_xcd;
     if (pass < 0 || tile >= ntile) return;
     bool live;
-    const long long c0 = tile_cell(tm, tile, threadIdx.x, g, live);
+    const long long c0 = tile_cell<TPB>(tm, tile, threadIdx.x, g, live);
     const long long c = live ? c0 : g.ncell - 1;
     const Nbr nb = neighbours(c, g);
     const long long ps = g.pstride;
-    double al[4], be[4];  // decay factors of the four target grids
+    // decay factors of the four target grids (rows 0..7), moment 0 (8, 9)
+    // and q (10), one column per thread, kept in LDS instead of registers
+    __shared__ double tl[11][TPB];
+    const int tid = threadIdx.x;
 #pragma unroll
-    for (int f = 0; f < 4; ++f) {
-        al[f] = tab[(long long)(rowbase + 2 * f) * g.ncell + c];
-        be[f] = tab[(long long)(rowbase + 2 * f + 1) * g.ncell + c];
-    }
-    double al0 = 1.0, be0 = 0.0, q0 = 0.0;
+    for (int f = 0; f < 8; ++f) tl[f][tid] = tab[(long long)(rowbase + f) * g.ncell + c];
     if (parity == 0) {
-        al0 = tab[(long long)kTabMom0 * g.ncell + c];
-        be0 = tab[(long long)(kTabMom0 + 1) * g.ncell + c];
-        q0 = tab[(long long)kTabQ * g.ncell + c];
+        tl[8][tid] = tab[(long long)kTabMom0 * g.ncell + c];
+        tl[9][tid] = tab[(long long)(kTabMom0 + 1) * g.ncell + c];
+        tl[10][tid] = tab[(long long)kTabQ * g.ncell + c];
     }
     const int MU1 = N + 2;
     const int L0 = parity + 2 * K * pass;
@@ -387,13 +389,13 @@ __global__ void __launch_bounds__(256) k_sweep_win(T* __restrict__ u,
                     if (d.x < 0) continue;
                     double alpha, beta, q = 0.0;
                     if (d.y == kTabMom0) {
-                        alpha = al0;
-                        beta = be0;
-                        q = q0;
+                        alpha = tl[8][tid];
+                        beta = tl[9][tid];
+                        q = tl[10][tid];
                     } else {
                         const int f = (d.y >> 1) & 3;
-                        alpha = f == 0 ? al[0] : f == 1 ? al[1] : f == 2 ? al[2] : al[3];
-                        beta = f == 0 ? be[0] : f == 1 ? be[1] : f == 2 ? be[2] : be[3];
+                        alpha = tl[2 * f][tid];
+                        beta = tl[2 * f + 1][tid];
                     }
                     T* ut = u + (long long)d.x * ps + c;
                     const double v = alpha * (double)ld_nt(ut) + beta * (q - (double)S[0][t][ty]);
@@ -415,24 +417,36 @@ __global__ void __launch_bounds__(256) k_sweep_win(T* __restrict__ u,
 int win_depth(int prec) { return prec == kF64 ? PM_WIN_K64 : PM_WIN_K32; }
 
 
+// Workgroup size and tile shape, measured on P39 64^3: 512- and 1024-thread
+// groups (up to 16 row segments stacked in z) were not faster in FP64 and
+// slower in FP32 (the LDS decay tables then cap the waves per CU).
+#ifndef PM_TPB
+#define PM_TPB 256
+#endif
+#ifndef PM_TILE_TY
+#define PM_TILE_TY 1
+#endif
+
 template <class T, int K>
 static void launch_win_t(T* u, const double* tab, int rowbase, WinArgs a, GridDesc g,
                          hipStream_t st) {
     using A = typename Acc<T>::type;
+    constexpr int TPB = PM_TPB;
     TileMap tm{0, 1, 1, 1, 1};
-    long long ntile = (g.ncell + 255) / 256;
+    long long ntile = (g.ncell + TPB - 1) / TPB;
     if (g.nx % 64 == 0) {
         tm.seg = g.nx / 64;
-        tm.ty = 1;  // a tile stacks 4 row segments along z
-        tm.tz = 4;
+        tm.ty = PM_TILE_TY;
+        tm.tz = TPB / 64 / PM_TILE_TY;
         tm.nty = (g.ny + tm.ty - 1) / tm.ty;
         tm.ntz = (g.nz + tm.tz - 1) / tm.tz;
         ntile = (long long)tm.seg * tm.nty * tm.ntz;
     }
     const int per_xcd = (int)((ntile + kXcds - 1) / kXcds);
     const unsigned nwg = (unsigned)((long long)kXcds * per_xcd * a.npass);
-    hipLaunchKernelGGL((k_sweep_win<T, K>), dim3(nwg), dim3(256), 0, st, u, tab, a.src, a.tgt,
-                       (const A*)a.coef, rowbase, a.N, a.parity, a.npass, per_xcd, ntile, tm, g);
+    hipLaunchKernelGGL((k_sweep_win<T, K, TPB>), dim3(nwg), dim3(TPB), 0, st, u, tab, a.src,
+                       a.tgt, (const A*)a.coef, rowbase, a.N, a.parity, a.npass, per_xcd, ntile,
+                       tm, g);
 }
 
 hipError_t launch_sweep_win(int prec, void* u, const double* tab, int rowbase, WinArgs a,
