@@ -162,6 +162,36 @@ def roofline(N, ncell, esz, times):
             "bytes_per_launch": byts, "ms_per_launch": round(per_launch * 1e3, 4)}
 
 
+def adjoint_timing(pm):
+    """Forward (recorded) and reverse pass of the gradient workload: P7,
+    64^3, 200 steps, checkpoints every 20 steps, FP64."""
+    import torch
+    import workloads
+    w = workloads.p7_adjoint()
+    dev = torch.device("cuda", 0)
+    pm.pm_set_precision(pm.PM_FP64)
+    pm.pm_bind_stream(torch.cuda.current_stream(dev).cuda_stream)
+    pm.pm_init(w.N, w.n, w.n, w.n, w.h, w.dt, w.sigma_a, w.sigma_s, w.q)
+    try:
+        for i in range(w.V):
+            pm.pm_write(i, w.moment(i))
+        pm.pm_set_checkpoint(w.checkpoint)
+        pm.pm_sync()
+        t0 = time.perf_counter()
+        pm.pm_step(w.nsteps)
+        pm.pm_sync()
+        t1 = time.perf_counter()
+        g = np.ones(w.shape)
+        pm.pm_grad(g)
+        t2 = time.perf_counter()
+    finally:
+        pm.pm_finalize()
+        pm.pm_bind_stream(0)
+    return {"workload": "%s: P%d, %d^3, %d steps, checkpoint every %d, fp64"
+                        % (w.name, w.N, w.n, w.nsteps, w.checkpoint),
+            "forward_ms": round((t1 - t0) * 1e3, 2), "grad_ms": round((t2 - t1) * 1e3, 2)}
+
+
 def cpu_baseline(w, steps):
     from oracle import c_oracle
     c_oracle.build(force=False)
@@ -186,6 +216,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--bf16", action="store_true", help="also time the BF16-storage probe")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the gradient timing")
     ap.add_argument("--copy-gib", type=float, default=2.0,
                     help="size of the calibration copy (0: skip)")
     args = ap.parse_args()
@@ -240,6 +271,11 @@ def main():
                                            / max(float(np.abs(b).max()) for b in s64))
         del sb
 
+    adjoint = None
+    if not args.no_adjoint:
+        say("bench: adjoint timing")
+        adjoint = adjoint_timing(pm)
+
     cpu = None
     if not args.no_cpu_baseline and w.n ** 3 * w.V > 1_000_000_000:
         say("bench: cpu oracle sample skipped for %s (host memory)" % w.name)
@@ -269,6 +305,7 @@ def main():
         "roofline": roof,
         "fp32": fp32,
         "bf16": bf16,
+        "adjoint": adjoint,
         "cpu_baseline": cpu,
         "copy_ceiling": copy,
         "state_check": {"max_abs": chk64[0], "nonfinite": chk64[1]},
