@@ -264,41 +264,43 @@ __device__ __forceinline__ void win_fetch(A (&r)[4], const T* __restrict__ u, in
     }
 }
 
-// Work decomposition: (tile of 256 cells) x (pass of K target degrees);
-// passes are independent (disjoint targets, read-only sources).  When rows
-// split into 64-cell segments (nx % 64 == 0) a tile is TY x TZ segments, one
-// wave per segment, so that most one-sided y/z neighbour rows are loaded by a
-// sibling wave of the same workgroup; otherwise a tile is 256 consecutive
-// cells.  Workgroups are dispatched round-robin over the 8 XCDs (id mod 8),
-// so the id is remapped to give every XCD a contiguous range of tiles (x
-// segment fastest, then y, then z): neighbour tiles then run at about the
-// same time on the same XCD and share its L2.  Within an XCD the most
-// expensive passes (highest degrees) go first.
+// Work decomposition: (tile of cells) x (pass of K target degrees); passes
+// are independent (disjoint targets, read-only sources).  When rows split
+// into segments of SW = 64 or 32 cells, a wave covers one segment of 64 / SW
+// consecutive rows and the waves of a workgroup are stacked along z, so that
+// most one-sided y/z neighbour rows are loaded by the same or a sibling wave;
+// otherwise a tile is TPB consecutive cells.  Workgroups are dispatched
+// round-robin over the 8 XCDs (id mod 8), so the id is remapped to give every
+// XCD a contiguous range of tiles (x segment fastest, then y, then z):
+// neighbour tiles then run at about the same time on the same XCD and share
+// its L2.  Within an XCD the most expensive passes (highest degrees) go
+// first.  (Interleaving the passes of a tile instead was measured slower.)
 constexpr int kXcds = 8;
 
 struct TileMap {
-    int seg;       // 64-cell segments per row (0: linear tiles of TPB cells)
-    int ty, tz;    // segments per tile in y and z (ty * tz == TPB / 64)
-    int nty, ntz;  // tiles per direction
+    int sw;        // segment width in cells: 64, 32, or 0 for linear tiles
+    int nseg;      // segments per row
+    int nty, ntz;  // tiles per direction (a tile: 64 / sw rows in y, TPB / 64 in z)
 };
 
 template <int TPB>
 __device__ __forceinline__ long long tile_cell(const TileMap& m, long long tile, int tid,
                                                const GridDesc& g, bool& live) {
-    if (m.seg == 0) {
+    if (m.sw == 0) {
         const long long c = tile * TPB + tid;
         live = c < g.ncell;
         return c;
     }
-    const long long xs = tile % m.seg;
-    const long long r = tile / m.seg;
+    const long long xs = tile % m.nseg;
+    const long long r = tile / m.nseg;
     const int yt = (int)(r % m.nty);
     const int zt = (int)(r / m.nty);
-    const int w = tid >> 6;
-    const int y = yt * m.ty + (w % m.ty);
-    const int z = zt * m.tz + (w / m.ty);
+    const int lane = tid & 63, w = tid >> 6;
+    const int x = (int)xs * m.sw + lane % m.sw;
+    const int y = yt * (64 / m.sw) + lane / m.sw;
+    const int z = zt * (TPB / 64) + w;
     live = y < g.ny && z < g.nz;
-    return (long long)(xs * 64 + (tid & 63)) + (long long)g.nx * ((long long)y + (long long)g.ny * z);
+    return (long long)x + (long long)g.nx * ((long long)y + (long long)g.ny * z);
 }
 
 template <class T, int K, int TPB>
@@ -417,14 +419,11 @@ __global__ void __launch_bounds__(TPB) k_sweep_win(T* __restrict__ u,
 int win_depth(int prec) { return prec == kF64 ? PM_WIN_K64 : PM_WIN_K32; }
 
 
-// Workgroup size and tile shape, measured on P39 64^3: 512- and 1024-thread
-// groups (up to 16 row segments stacked in z) were not faster in FP64 and
-// slower in FP32 (the LDS decay tables then cap the waves per CU).
+// Workgroup size, measured on P39 64^3: 512- and 1024-thread groups (up to
+// 16 row segments stacked in z) were not faster in FP64 and slower in FP32
+// (the LDS decay tables then cap the waves per CU).
 #ifndef PM_TPB
 #define PM_TPB 256
-#endif
-#ifndef PM_TILE_TY
-#define PM_TILE_TY 1
 #endif
 
 template <class T, int K>
@@ -432,15 +431,15 @@ static void launch_win_t(T* u, const double* tab, int rowbase, WinArgs a, GridDe
                          hipStream_t st) {
     using A = typename Acc<T>::type;
     constexpr int TPB = PM_TPB;
-    TileMap tm{0, 1, 1, 1, 1};
+    TileMap tm{0, 1, 1, 1};
     long long ntile = (g.ncell + TPB - 1) / TPB;
-    if (g.nx % 64 == 0) {
-        tm.seg = g.nx / 64;
-        tm.ty = PM_TILE_TY;
-        tm.tz = TPB / 64 / PM_TILE_TY;
-        tm.nty = (g.ny + tm.ty - 1) / tm.ty;
-        tm.ntz = (g.nz + tm.tz - 1) / tm.tz;
-        ntile = (long long)tm.seg * tm.nty * tm.ntz;
+    const int sw = g.nx % 64 == 0 ? 64 : g.nx % 32 == 0 ? 32 : 0;
+    if (sw) {
+        tm.sw = sw;
+        tm.nseg = g.nx / sw;
+        tm.nty = (g.ny + 64 / sw - 1) / (64 / sw);
+        tm.ntz = (g.nz + TPB / 64 - 1) / (TPB / 64);
+        ntile = (long long)tm.nseg * tm.nty * tm.ntz;
     }
     const int per_xcd = (int)((ntile + kXcds - 1) / kXcds);
     const unsigned nwg = (unsigned)((long long)kXcds * per_xcd * a.npass);

@@ -49,9 +49,12 @@ def test_p3_pulse_full_fp64():
 @pytest.mark.parametrize("N,shape", [(0, (3, 4, 5)), (1, (4, 4, 4)), (3, (2, 3, 4)), (2, (1, 1, 7)),
                                      (3, (5, 1, 1)), (2, (1, 6, 1)), (7, (3, 5, 7)), (3, (5, 7, 9)),
                                      (4, (1, 1, 1)), (3, (3, 2, 67)),
-                                     # rows of 64 / 128 cells: the LDS-staged tile kernel
+                                     # rows of whole 64- or 32-cell segments: row-tiled
+                                     # workgroups (ragged in y and z too)
                                      (7, (4, 6, 64)), (5, (2, 3, 128)), (3, (6, 4, 128)),
-                                     (4, (2, 2, 64)), (2, (2, 1, 64)), (3, (3, 2, 64))])
+                                     (4, (2, 2, 64)), (2, (2, 1, 64)), (3, (3, 2, 64)),
+                                     (5, (5, 3, 32)), (3, (4, 7, 96)), (4, (3, 2, 160)),
+                                     (2, (9, 1, 32))])
 def test_small_and_ragged_fp64(N, shape):
     """Tiny, degenerate (n_d = 1, a single cell) and ragged grids whose cell
     counts are not multiples of the 64-lane wave or the 256-thread block."""
