@@ -9,6 +9,7 @@
 
 #include <cmath>
 #include <cstdint>
+#include <type_traits>
 
 #include "kernels.h"
 
@@ -250,60 +251,151 @@ hipError_t launch_sweep(int prec, void* u, const double* tab, Schedule s, GridDe
 // next column are requested as soon as its current ones are consumed
 // (one-column software pipeline).
 
-template <class T, class A>
-__device__ __forceinline__ void win_fetch(A (&r)[4], const T* __restrict__ u, int2 d,
-                                          const Nbr& nb, long long ps) {
-    if (d.x >= 0) {
-        const T* p = u + (long long)d.x * ps + nb.c;
-        r[0] = (A)ld(p);
-        r[1] = (A)ld(p + ((d.y & 1) ? nb.off[1] : nb.off[0]));
-        r[2] = (A)ld(p + ((d.y & 2) ? nb.off[3] : nb.off[2]));
-        r[3] = (A)ld(p + ((d.y & 4) ? nb.off[5] : nb.off[4]));
+// ---- several consecutive x-cells per lane --------------------------------
+// A lane owns CPL consecutive cells of a row; its plane accesses are vector
+// loads/stores of CPL elements (8 to 16 bytes), so a wave moves 512 B to 1 KB
+// per instruction whatever the storage type.
+template <class T, int CPL> struct Pack;
+template <> struct Pack<double, 1> { using V = double; using S1 = double; };
+template <> struct Pack<double, 2> { using V = double __attribute__((ext_vector_type(2))); using S1 = double; };
+template <> struct Pack<float, 1> { using V = float; using S1 = float; };
+template <> struct Pack<float, 2> { using V = float __attribute__((ext_vector_type(2))); using S1 = float; };
+template <> struct Pack<float, 4> { using V = float __attribute__((ext_vector_type(4))); using S1 = float; };
+template <> struct Pack<bf16s, 1> { using V = uint16_t; using S1 = uint16_t; };
+template <> struct Pack<bf16s, 2> { using V = uint32_t; using S1 = uint16_t; };
+template <> struct Pack<bf16s, 4> { using V = uint32_t __attribute__((ext_vector_type(2))); using S1 = uint16_t; };
+
+__device__ __forceinline__ float bf_lo(uint32_t w) { return __uint_as_float(w << 16); }
+__device__ __forceinline__ float bf_hi(uint32_t w) { return __uint_as_float(w & 0xffff0000u); }
+__device__ __forceinline__ uint32_t bf_bits(double v) {
+    bf16s t;
+    st(&t, v);
+    return t.b;
+}
+
+template <class T, int CPL, class A>
+__device__ __forceinline__ void unpack(typename Pack<T, CPL>::V v, A (&o)[CPL]) {
+    if constexpr (std::is_same<T, bf16s>::value) {
+        if constexpr (CPL == 1) {
+            o[0] = __uint_as_float((uint32_t)v << 16);
+        } else if constexpr (CPL == 2) {
+            o[0] = bf_lo(v);
+            o[1] = bf_hi(v);
+        } else {
+            o[0] = bf_lo(v.x);
+            o[1] = bf_hi(v.x);
+            o[2] = bf_lo(v.y);
+            o[3] = bf_hi(v.y);
+        }
+    } else if constexpr (CPL == 1) {
+        o[0] = v;
     } else {
-        r[0] = r[1] = r[2] = r[3] = (A)0;
+#pragma unroll
+        for (int k = 0; k < CPL; ++k) o[k] = v[k];
+    }
+}
+
+template <class T, int CPL>
+__device__ __forceinline__ typename Pack<T, CPL>::V pack(const double (&v)[CPL]) {
+    using V = typename Pack<T, CPL>::V;
+    V r;
+    if constexpr (std::is_same<T, bf16s>::value) {
+        if constexpr (CPL == 1) {
+            r = (uint16_t)bf_bits(v[0]);
+        } else if constexpr (CPL == 2) {
+            r = bf_bits(v[0]) | (bf_bits(v[1]) << 16);
+        } else {
+            r.x = bf_bits(v[0]) | (bf_bits(v[1]) << 16);
+            r.y = bf_bits(v[2]) | (bf_bits(v[3]) << 16);
+        }
+    } else if constexpr (CPL == 1) {
+        r = (T)v[0];
+    } else {
+#pragma unroll
+        for (int k = 0; k < CPL; ++k) r[k] = (T)v[k];
+    }
+    return r;
+}
+
+template <class T> __device__ __forceinline__ float s1_val(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+template <class T> __device__ __forceinline__ T s1_val(T x) { return x; }
+
+// Raw values of one source for one lane: its CPL centre cells, the CPL cells
+// of the one-sided y and z neighbour rows, and the one x neighbour outside
+// the lane's own cells.
+template <class T, int CPL>
+struct Raw {
+    typename Pack<T, CPL>::V c, y, z;
+    typename Pack<T, CPL>::S1 xe;
+};
+
+struct LaneNbr {
+    long long c0;       // first cell of the lane
+    int xep, xem;       // offset of the outside x neighbour: forward, backward
+    int yp, ym, zp, zm; // row offsets of the y / z neighbours: forward, backward
+};
+
+template <class T, int CPL>
+__device__ __forceinline__ void win_fetch(Raw<T, CPL>& r, const T* __restrict__ u, int2 d,
+                                          const LaneNbr& nb, long long ps) {
+    using V = typename Pack<T, CPL>::V;
+    using S1 = typename Pack<T, CPL>::S1;
+    if (d.x >= 0) {
+        const T* p = u + (long long)d.x * ps + nb.c0;
+        r.c = *(const V*)p;
+        r.y = *(const V*)(p + ((d.y & 2) ? nb.ym : nb.yp));
+        r.z = *(const V*)(p + ((d.y & 4) ? nb.zm : nb.zp));
+        r.xe = *(const S1*)(p + ((d.y & 1) ? nb.xem : nb.xep));
+    } else {
+        r.c = V{};
+        r.y = V{};
+        r.z = V{};
+        r.xe = S1{};
     }
 }
 
 // Work decomposition: (tile of cells) x (pass of K target degrees); passes
 // are independent (disjoint targets, read-only sources).  When rows split
-// into segments of SW = 64 or 32 cells, a wave covers one segment of 64 / SW
-// consecutive rows and the waves of a workgroup are stacked along z, so that
-// most one-sided y/z neighbour rows are loaded by the same or a sibling wave;
-// otherwise a tile is TPB consecutive cells.  Workgroups are dispatched
-// round-robin over the 8 XCDs (id mod 8), so the id is remapped to give every
-// XCD a contiguous range of tiles (x segment fastest, then y, then z):
-// neighbour tiles then run at about the same time on the same XCD and share
-// its L2.  Within an XCD the most expensive passes (highest degrees) go
-// first.  (Interleaving the passes of a tile instead was measured slower.)
+// into segments of SW cells (SW = 64, 32 or 16 lanes of CPL cells), a wave
+// covers one segment of 64 * CPL / SW consecutive rows and the waves of a
+// workgroup are stacked along z, so that most one-sided y/z neighbour rows
+// are loaded by the same or a sibling wave; otherwise a tile is TPB * CPL
+// consecutive cells.  Workgroups are dispatched round-robin over the 8 XCDs
+// (id mod 8), so the id is remapped to give every XCD a contiguous range of
+// tiles (x segment fastest, then y, then z): neighbour tiles then run at
+// about the same time on the same XCD and share its L2.  Within an XCD the
+// most expensive passes (highest degrees) go first.  (Interleaving the
+// passes of a tile instead was measured slower.)
 constexpr int kXcds = 8;
 
 struct TileMap {
-    int sw;        // segment width in cells: 64, 32, or 0 for linear tiles
+    int sw;        // segment width in cells, or 0 for linear tiles
     int nseg;      // segments per row
-    int nty, ntz;  // tiles per direction (a tile: 64 / sw rows in y, TPB / 64 in z)
+    int nty, ntz;  // tiles per direction
 };
 
-template <int TPB>
+template <int TPB, int CPL>
 __device__ __forceinline__ long long tile_cell(const TileMap& m, long long tile, int tid,
                                                const GridDesc& g, bool& live) {
     if (m.sw == 0) {
-        const long long c = tile * TPB + tid;
+        const long long c = (tile * TPB + tid) * CPL;
         live = c < g.ncell;
         return c;
     }
+    const int ls = m.sw / CPL;  // lanes per segment row
     const long long xs = tile % m.nseg;
     const long long r = tile / m.nseg;
     const int yt = (int)(r % m.nty);
     const int zt = (int)(r / m.nty);
     const int lane = tid & 63, w = tid >> 6;
-    const int x = (int)xs * m.sw + lane % m.sw;
-    const int y = yt * (64 / m.sw) + lane / m.sw;
+    const int x = (int)xs * m.sw + (lane % ls) * CPL;
+    const int y = yt * (64 / ls) + lane / ls;
     const int z = zt * (TPB / 64) + w;
     live = y < g.ny && z < g.nz;
     return (long long)x + (long long)g.nx * ((long long)y + (long long)g.ny * z);
 }
 
-template <class T, int K, int TPB>
+template <class T, int K, int TPB, int CPL>
 __global__ void __launch_bounds__(TPB) k_sweep_win(T* __restrict__ u,
                                                    const double* __restrict__ tab,
                                                    const int2* __restrict__ src,
@@ -313,26 +405,44 @@ __global__ void __launch_bounds__(TPB) k_sweep_win(T* __restrict__ u,
                                                    int per_xcd, long long ntile, TileMap tm,
                                                    GridDesc g) {
     using A = typename Acc<T>::type;
+    using V = typename Pack<T, CPL>::V;
     const int xcd = blockIdx.x % kXcds;
     const int j = blockIdx.x / kXcds;
     const long long tile = (long long)xcd * per_xcd + (j % per_xcd);
     const int pass = npass - 1 - j / per_xcd;
     if (pass < 0 || tile >= ntile) return;
     bool live;
-    const long long c0 = tile_cell<TPB>(tm, tile, threadIdx.x, g, live);
-    const long long c = live ? c0 : g.ncell - 1;
-    const Nbr nb = neighbours(c, g);
+    const long long cl = tile_cell<TPB, CPL>(tm, tile, threadIdx.x, g, live);
+    LaneNbr nb;
+    {
+        const long long c = live ? cl : g.ncell - CPL;
+        const Nbr n0 = neighbours(c, g);
+        const int x0 = (int)(c % g.nx);
+        nb.c0 = c;
+        nb.xep = (x0 + CPL == g.nx) ? CPL - g.nx : CPL;
+        nb.xem = (x0 == 0) ? g.nx - 1 : -1;
+        nb.yp = n0.off[2];
+        nb.ym = n0.off[3];
+        nb.zp = n0.off[4];
+        nb.zm = n0.off[5];
+    }
     const long long ps = g.pstride;
     // decay factors of the four target grids (rows 0..7), moment 0 (8, 9)
-    // and q (10), one column per thread, kept in LDS instead of registers
-    __shared__ double tl[11][TPB];
+    // and q (10) for the lane's cells, kept in LDS instead of registers
+    __shared__ double tl[11][TPB * CPL];
     const int tid = threadIdx.x;
 #pragma unroll
-    for (int f = 0; f < 8; ++f) tl[f][tid] = tab[(long long)(rowbase + f) * g.ncell + c];
+    for (int f = 0; f < 8; ++f)
+#pragma unroll
+        for (int k = 0; k < CPL; ++k)
+            tl[f][tid * CPL + k] = tab[(long long)(rowbase + f) * g.ncell + nb.c0 + k];
     if (parity == 0) {
-        tl[8][tid] = tab[(long long)kTabMom0 * g.ncell + c];
-        tl[9][tid] = tab[(long long)(kTabMom0 + 1) * g.ncell + c];
-        tl[10][tid] = tab[(long long)kTabQ * g.ncell + c];
+#pragma unroll
+        for (int k = 0; k < CPL; ++k) {
+            tl[8][tid * CPL + k] = tab[(long long)kTabMom0 * g.ncell + nb.c0 + k];
+            tl[9][tid * CPL + k] = tab[(long long)(kTabMom0 + 1) * g.ncell + nb.c0 + k];
+            tl[10][tid * CPL + k] = tab[(long long)kTabQ * g.ncell + nb.c0 + k];
+        }
     }
     const int MU1 = N + 2;
     const int L0 = parity + 2 * K * pass;
@@ -341,16 +451,20 @@ __global__ void __launch_bounds__(TPB) k_sweep_win(T* __restrict__ u,
     const int2* td = tgt + (long long)pass * MU1 * K * 2;
     const A* cf = coef + (long long)pass * MU1 * (K + 1) * 20;
 
-    A R[K + 1][2][4];  // raw values of the current source column
-    A S[3][K][2];      // partial sums: target columns mu-1, mu, mu+1
+    Raw<T, CPL> R[K + 1][2];  // raw values of the current source column
+    A S[3][K][2][CPL];        // partial sums: target columns mu-1, mu, mu+1
 #pragma unroll
     for (int b = 0; b <= K; ++b)
 #pragma unroll
-        for (int ty = 0; ty < 2; ++ty) win_fetch<T, A>(R[b][ty], u, sd[b * 2 + ty], nb, ps);
+        for (int ty = 0; ty < 2; ++ty) win_fetch<T, CPL>(R[b][ty], u, sd[b * 2 + ty], nb, ps);
 #pragma unroll
     for (int w = 0; w < 3; ++w)
 #pragma unroll
-        for (int t = 0; t < K; ++t) S[w][t][0] = S[w][t][1] = (A)0;
+        for (int t = 0; t < K; ++t)
+#pragma unroll
+            for (int ty = 0; ty < 2; ++ty)
+#pragma unroll
+                for (int k = 0; k < CPL; ++k) S[w][t][ty][k] = (A)0;
 
     for (int mu = 0; mu <= mumax + 1; ++mu) {
         const int2* sdc = sd + mu * (K + 1) * 2;
@@ -361,22 +475,38 @@ __global__ void __launch_bounds__(TPB) k_sweep_win(T* __restrict__ u,
         for (int b = 0; b <= K; ++b) {
 #pragma unroll
             for (int ty = 0; ty < 2; ++ty) {
-                const A dx = R[b][ty][1] - R[b][ty][0];
-                const A dy = R[b][ty][2] - R[b][ty][0];
-                const A dz = R[b][ty][3] - R[b][ty][0];
-                const bool here = sdc[b * 2 + ty].x >= 0;
-                if (mu <= mumax) win_fetch<T, A>(R[b][ty], u, sdn[b * 2 + ty], nb, ps);
-                if (!here) continue;
+                const int2 e = sdc[b * 2 + ty];
+                A vc[CPL], vy[CPL], vz[CPL];
+                unpack<T, CPL, A>(R[b][ty].c, vc);
+                unpack<T, CPL, A>(R[b][ty].y, vy);
+                unpack<T, CPL, A>(R[b][ty].z, vz);
+                const A xv = (A)s1_val<T>(R[b][ty].xe);
+                A dx[CPL], dy[CPL], dz[CPL];
+                const bool back = e.y & 1;
+#pragma unroll
+                for (int k = 0; k < CPL; ++k) {
+                    const A xn = back ? (k > 0 ? vc[k > 0 ? k - 1 : 0] : xv)
+                                      : (k < CPL - 1 ? vc[k < CPL - 1 ? k + 1 : 0] : xv);
+                    dx[k] = xn - vc[k];
+                    dy[k] = vy[k] - vc[k];
+                    dz[k] = vz[k] - vc[k];
+                }
+                if (mu <= mumax) win_fetch<T, CPL>(R[b][ty], u, sdn[b * 2 + ty], nb, ps);
+                if (e.x < 0) continue;
 #pragma unroll
                 for (int side = 0; side < 2; ++side) {
                     const int t = side == 0 ? b : b - 1;
                     if (t < 0 || t >= K) continue;
-                    const A* k = cfc + ((b * 2 + ty) * 2 + side) * 5;
-                    S[0][t][ty] += k[0] * dx;
-                    S[0][t][1 - ty] += k[1] * dy;
-                    S[1][t][ty] += k[2] * dz;
-                    S[2][t][ty] += k[3] * dx;
-                    S[2][t][1 - ty] += k[4] * dy;
+                    const A* kk = cfc + ((b * 2 + ty) * 2 + side) * 5;
+                    const A k0 = kk[0], k1 = kk[1], k2 = kk[2], k3 = kk[3], k4 = kk[4];
+#pragma unroll
+                    for (int k = 0; k < CPL; ++k) {
+                        S[0][t][ty][k] += k0 * dx[k];
+                        S[0][t][1 - ty][k] += k1 * dy[k];
+                        S[1][t][ty][k] += k2 * dz[k];
+                        S[2][t][ty][k] += k3 * dx[k];
+                        S[2][t][1 - ty][k] += k4 * dy[k];
+                    }
                 }
             }
         }
@@ -389,74 +519,96 @@ __global__ void __launch_bounds__(TPB) k_sweep_win(T* __restrict__ u,
                 for (int ty = 0; ty < 2; ++ty) {
                     const int2 d = tdc[t * 2 + ty];
                     if (d.x < 0) continue;
-                    double alpha, beta, q = 0.0;
-                    if (d.y == kTabMom0) {
-                        alpha = tl[8][tid];
-                        beta = tl[9][tid];
-                        q = tl[10][tid];
-                    } else {
-                        const int f = (d.y >> 1) & 3;
-                        alpha = tl[2 * f][tid];
-                        beta = tl[2 * f + 1][tid];
+                    const int ra = d.y == kTabMom0 ? 8 : 2 * ((d.y >> 1) & 3);
+                    T* ut = u + (long long)d.x * ps + nb.c0;
+                    A old[CPL];
+                    unpack<T, CPL, A>(__builtin_nontemporal_load((const V*)ut), old);
+                    double nv[CPL];
+#pragma unroll
+                    for (int k = 0; k < CPL; ++k) {
+                        const double q = d.y == kTabMom0 ? tl[10][tid * CPL + k] : 0.0;
+                        nv[k] = tl[ra][tid * CPL + k] * (double)old[k] +
+                                tl[ra + 1][tid * CPL + k] * (q - (double)S[0][t][ty][k]);
                     }
-                    T* ut = u + (long long)d.x * ps + c;
-                    const double v = alpha * (double)ld_nt(ut) + beta * (q - (double)S[0][t][ty]);
-                    if (live) st_nt(ut, v);
+                    if (live) __builtin_nontemporal_store(pack<T, CPL>(nv), (V*)ut);
                 }
             }
         }
 #pragma unroll
         for (int t = 0; t < K; ++t)
 #pragma unroll
-            for (int ty = 0; ty < 2; ++ty) {
-                S[0][t][ty] = S[1][t][ty];
-                S[1][t][ty] = S[2][t][ty];
-                S[2][t][ty] = (A)0;
-            }
+            for (int ty = 0; ty < 2; ++ty)
+#pragma unroll
+                for (int k = 0; k < CPL; ++k) {
+                    S[0][t][ty][k] = S[1][t][ty][k];
+                    S[1][t][ty][k] = S[2][t][ty][k];
+                    S[2][t][ty][k] = (A)0;
+                }
     }
 }
 
 int win_depth(int prec) { return prec == kF64 ? PM_WIN_K64 : PM_WIN_K32; }
 
 
-// Workgroup size, measured on P39 64^3: 512- and 1024-thread groups (up to
-// 16 row segments stacked in z) were not faster in FP64 and slower in FP32
-// (the LDS decay tables then cap the waves per CU).
-#ifndef PM_TPB
-#define PM_TPB 256
+// Launch shape, measured on P39 64^3.  Cells per lane: 1 for FP64 and FP32
+// (2 was slower: more registers per wave), 2 for BF16 (4-byte accesses; +7%).
+// Workgroups of 256 / CPL threads keep the LDS decay tables at 22.5 KB;
+// 512- and 1024-thread groups (up to 16 row segments stacked in z) were not
+// faster in FP64 and slower in FP32.
+#ifndef PM_CPL64
+#define PM_CPL64 1
+#endif
+#ifndef PM_CPL32
+#define PM_CPL32 1
+#endif
+#ifndef PM_CPL16
+#define PM_CPL16 2
 #endif
 
-template <class T, int K>
+template <class T, int K, int CPL>
 static void launch_win_t(T* u, const double* tab, int rowbase, WinArgs a, GridDesc g,
                          hipStream_t st) {
     using A = typename Acc<T>::type;
-    constexpr int TPB = PM_TPB;
+    constexpr int TPB = 256 / CPL;
     TileMap tm{0, 1, 1, 1};
-    long long ntile = (g.ncell + TPB - 1) / TPB;
-    const int sw = g.nx % 64 == 0 ? 64 : g.nx % 32 == 0 ? 32 : 0;
+    long long ntile = (g.ncell / CPL + TPB - 1) / TPB;
+    int sw = 0;
+    for (int lanes = 64; lanes >= 16 && !sw; lanes /= 2)
+        if (g.nx % (lanes * CPL) == 0) sw = lanes * CPL;
     if (sw) {
         tm.sw = sw;
         tm.nseg = g.nx / sw;
-        tm.nty = (g.ny + 64 / sw - 1) / (64 / sw);
+        tm.nty = (g.ny + 64 * CPL / sw - 1) / (64 * CPL / sw);
         tm.ntz = (g.nz + TPB / 64 - 1) / (TPB / 64);
         ntile = (long long)tm.nseg * tm.nty * tm.ntz;
     }
     const int per_xcd = (int)((ntile + kXcds - 1) / kXcds);
     const unsigned nwg = (unsigned)((long long)kXcds * per_xcd * a.npass);
-    hipLaunchKernelGGL((k_sweep_win<T, K, TPB>), dim3(nwg), dim3(TPB), 0, st, u, tab, a.src,
-                       a.tgt, (const A*)a.coef, rowbase, a.N, a.parity, a.npass, per_xcd, ntile,
-                       tm, g);
+    hipLaunchKernelGGL((k_sweep_win<T, K, TPB, CPL>), dim3(nwg), dim3(TPB), 0, st, u, tab,
+                       a.src, a.tgt, (const A*)a.coef, rowbase, a.N, a.parity, a.npass, per_xcd,
+                       ntile, tm, g);
 }
 
 hipError_t launch_sweep_win(int prec, void* u, const double* tab, int rowbase, WinArgs a,
                             GridDesc g, hipStream_t st) {
     if (a.K != win_depth(prec)) return hipErrorInvalidValue;
-    if (prec == kF64)
-        launch_win_t<double, PM_WIN_K64>((double*)u, tab, rowbase, a, g, st);
-    else if (prec == kF32)
-        launch_win_t<float, PM_WIN_K32>((float*)u, tab, rowbase, a, g, st);
-    else
-        launch_win_t<bf16s, PM_WIN_K32>((bf16s*)u, tab, rowbase, a, g, st);
+    // several cells per lane need whole lane groups within every row
+    if (prec == kF64) {
+        if (PM_CPL64 > 1 && g.nx % PM_CPL64 == 0)
+            launch_win_t<double, PM_WIN_K64, PM_CPL64>((double*)u, tab, rowbase, a, g, st);
+        else
+            launch_win_t<double, PM_WIN_K64, 1>((double*)u, tab, rowbase, a, g, st);
+    } else if (prec == kF32) {
+        if (PM_CPL32 > 1 && g.nx % PM_CPL32 == 0)
+            launch_win_t<float, PM_WIN_K32, PM_CPL32>((float*)u, tab, rowbase, a, g, st);
+        else
+            launch_win_t<float, PM_WIN_K32, 1>((float*)u, tab, rowbase, a, g, st);
+    } else {
+        if (PM_CPL16 > 1 && g.nx % PM_CPL16 == 0)
+            launch_win_t<bf16s, PM_WIN_K32, PM_CPL16>((bf16s*)u, tab, rowbase, a, g, st);
+        else
+            launch_win_t<bf16s, PM_WIN_K32, 1>((bf16s*)u, tab, rowbase, a, g, st);
+    }
     return hipGetLastError();
 }
 

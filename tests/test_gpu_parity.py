@@ -248,3 +248,18 @@ def test_merged_schedule(shape):
     for k, v in out.items():
         assert relerr(v, ref) <= 1e-13, k
     assert relerr(out[(1, 0)], out[(0, 0)]) <= 1e-14
+
+
+@pytest.mark.parametrize("shape", [(4, 6, 64), (3, 5, 12), (2, 3, 7), (3, 2, 160)])
+def test_bf16_and_fp32_small_shapes(shape):
+    """BF16 storage (two cells per lane where rows have an even length, one
+    otherwise) and FP32 against the FP64 oracle on small grids."""
+    N = 5
+    sa, ss, q, u = rand_problem(N, shape, 31)
+    h, dt = 0.2, 0.07
+    ref = st.run(st.Setup(N, shape, h, dt, sa, ss, q), u, 4)
+    e32 = relerr(gpu_run(N, shape, h, dt, sa, ss, q, u, 4, prec=pm.PM_FP32), ref)
+    e16 = relerr(gpu_run(N, shape, h, dt, sa, ss, q, u, 4, prec=pm.PM_BF16), ref)
+    say("small %s fp32 %.2e bf16 %.2e" % (shape, e32, e16))
+    assert e32 <= FP32_TOL
+    assert e16 <= 2e-2
