@@ -55,8 +55,6 @@ struct Ctx {
     void* u = nullptr;
     double* tab = nullptr;
     double* sig = nullptr;  // sigma_a, sigma_s (device copies)
-    void* sched_mem = nullptr;
-    pm::Schedule sched[2]{};  // [0] even targets, [1] odd targets
     void* win_mem = nullptr;  // window sweep streams (both parities)
     pm::WinArgs win[2]{};
     double* plane64 = nullptr;
@@ -123,7 +121,6 @@ void release() {
     dfree(C.u);
     dfree(C.tab);
     dfree(C.sig);
-    dfree(C.sched_mem);
     dfree(C.win_mem);
     dfree(C.plane64);
     dfree(C.red);
@@ -147,59 +144,6 @@ long long plane_stride(long long ncell) {
     long long s = (ncell + 63) / 64 * 64;
     if ((s & (s - 1)) == 0 && s >= 4096) s += 64;
     return s;
-}
-
-int build_schedules() {
-    const pm::Layout& L = C.L;
-    std::vector<pm::FluxEntry> fe = pm::flux_entries(C.N);
-    std::vector<std::vector<const pm::FluxEntry*>> by_row(C.V);
-    for (const auto& e : fe) by_row[e.row].push_back(&e);
-    std::vector<pm::SweepRow> rows[2];
-    std::vector<pm::SweepEnt> ents[2];
-    for (int slot = 0; slot < C.V; ++slot) {
-        const int i = L.moment_of[slot];
-        int l, m;
-        pm::moment_lm(i, l, m);
-        const int bits = pm::grid_bits(l, m);
-        const int par = __builtin_popcount(bits) & 1;
-        pm::SweepRow r;
-        r.slot = slot;
-        r.tab = (i == 0) ? pm::kTabMom0 : 2 * L.order_of[i];
-        r.begin = (int)ents[par].size();
-        for (const pm::FluxEntry* e : by_row[i]) {
-            const int stag = (bits >> e->dir) & 1;  // target staggered in d: forward difference
-            pm::SweepEnt s;
-            s.slot = L.slot_of[e->col];
-            s.nb = 2 * e->dir + (stag ? 0 : 1);
-            s.K = (stag ? 1.0 : -1.0) * e->val / C.dx;
-            ents[par].push_back(s);
-        }
-        r.end = (int)ents[par].size();
-        rows[par].push_back(r);
-    }
-    size_t bytes = 0;
-    size_t off_rows[2], off_ents[2];
-    for (int p = 0; p < 2; ++p) {
-        off_rows[p] = bytes;
-        bytes += (rows[p].size() * sizeof(pm::SweepRow) + 15) / 16 * 16;
-        off_ents[p] = bytes;
-        bytes += (ents[p].size() * sizeof(pm::SweepEnt) + 15) / 16 * 16;
-    }
-    int rc = dmalloc(&C.sched_mem, bytes, "schedule");
-    if (rc) return rc;
-    for (int p = 0; p < 2; ++p) {
-        char* base = (char*)C.sched_mem;
-        if (!rows[p].empty())
-            HIPCHK(hipMemcpy(base + off_rows[p], rows[p].data(), rows[p].size() * sizeof(pm::SweepRow),
-                             hipMemcpyHostToDevice));
-        if (!ents[p].empty())
-            HIPCHK(hipMemcpy(base + off_ents[p], ents[p].data(), ents[p].size() * sizeof(pm::SweepEnt),
-                             hipMemcpyHostToDevice));
-        C.sched[p].rows = (const pm::SweepRow*)(base + off_rows[p]);
-        C.sched[p].nrows = (int)rows[p].size();
-        C.sched[p].ents = (const pm::SweepEnt*)(base + off_ents[p]);
-    }
-    return PM_OK;
 }
 
 // Streams of the window sweep (layout documented in kernels.h).  Every
@@ -315,7 +259,7 @@ int build_window_tables() {
 // One sweep of the given parity; `full` selects tau = dt for the odd grids
 // (two merged odd half steps).
 int sweep(void* u, int parity, bool full = false) {
-    if (C.sched[parity].nrows == 0) return PM_OK;
+    if (C.win[parity].npass == 0) return PM_OK;
     hipEvent_t a = nullptr, b = nullptr;
     if (C.timing) {
         HIPCHK(hipEventCreate(&a));
@@ -451,7 +395,6 @@ int pm_init(int N, int nx, int ny, int nz, double dx, double dt, const double* s
     TRY(dmalloc(&C.plane64, sizeof(double) * (size_t)ncell, "plane"));
     TRY(dmalloc(&C.red, sizeof(double) * (C.npart + 1), "reduction"));
     TRY(dmalloc(&C.redc, sizeof(unsigned long long) * (C.npart + 1), "reduction"));
-    TRY(build_schedules());
     TRY(build_window_tables());
     hipStream_t s = C.stream();
     auto dev = [&](hipError_t err, const char* what) -> int {
@@ -574,11 +517,12 @@ int pm_grad(const double* dL_du0, double* dsa, double* dss) {
     const long long T = C.rec_steps;
     const int ck = C.ck;
     void *lam = nullptr, *w = nullptr, *ua = nullptr, *ub = nullptr, *seg = nullptr;
-    double *grad = nullptr, *outg = nullptr;
+    double *grad = nullptr, *outg = nullptr, *gpass = nullptr;
     const long long before = C.dev_bytes;
     const bool timing = C.timing;
     auto cleanup = [&]() {
         dfree(lam); dfree(w); dfree(ua); dfree(ub); dfree(seg); dfree(grad); dfree(outg);
+        dfree(gpass);
         C.dev_bytes = before;
         C.timing = timing;
     };
@@ -600,10 +544,13 @@ int pm_grad(const double* dL_du0, double* dsa, double* dss) {
         }                                                                              \
     } while (0)
     const int segs = T > 0 ? ck : 1;
+    const int np0 = C.win[0].npass, np1 = C.win[1].npass;
+    const size_t gpb = sizeof(double) * pm::kGradRows * (size_t)n;  // one pass of gradient rows
     {
         size_t fr = 0, tot = 0;
         HIPCHK(hipMemGetInfo(&fr, &tot));
-        const size_t need = SB * (size_t)(4 + segs) + sizeof(double) * (pm::kGradRows + 2) * (size_t)n;
+        const size_t need = SB * (size_t)(4 + segs) + gpb * (size_t)(np0 + np1 + 1) +
+                            sizeof(double) * 2 * (size_t)n;
         if (need > fr)
             return fail(PM_ENOMEM, "gradient pass needs " + std::to_string(need) + " bytes, " +
                                        std::to_string(fr) + " free on the device");
@@ -613,13 +560,15 @@ int pm_grad(const double* dL_du0, double* dsa, double* dss) {
     TRYG(dmalloc(&ua, SB, "recompute a"));
     TRYG(dmalloc(&ub, SB, "recompute b"));
     TRYG(dmalloc(&seg, SB * (size_t)segs, "segment states"));
-    TRYG(dmalloc(&grad, sizeof(double) * pm::kGradRows * (size_t)n, "gradient accumulators"));
+    TRYG(dmalloc(&gpass, gpb * (size_t)(np0 + np1), "per-pass gradient rows"));
+    TRYG(dmalloc(&grad, gpb, "gradient accumulators"));
     TRYG(dmalloc(&outg, sizeof(double) * 2 * (size_t)n, "gradient output"));
     HIPG(pm::launch_fill_zero(lam, (long long)SB, s));
     HIPG(pm::launch_fill_zero(w, (long long)SB, s));
-    HIPG(pm::launch_fill_zero(grad, (long long)(sizeof(double) * pm::kGradRows * n), s));
+    HIPG(pm::launch_fill_zero(gpass, (long long)(gpb * (np0 + np1)), s));
     HIPG(hipMemcpyAsync(C.plane64, dL_du0, sizeof(double) * n, hipMemcpyHostToDevice, s));
     HIPG(pm::launch_from_f64(C.prec, C.plane64, C.plane(lam, C.L.slot_of[0]), n, s));
+    double* gp_par[2] = {gpass, gpass + (size_t)np0 * pm::kGradRows * (size_t)n};
     C.timing = false;
     const long long nseg = (T + ck - 1) / ck;
     for (long long gseg = nseg - 1; gseg >= 0; --gseg) {
@@ -637,15 +586,21 @@ int pm_grad(const double* dL_du0, double* dsa, double* dss) {
             TRYG(sweep(ua, 1));
             HIPG(hipMemcpyAsync(ub, ua, SB, hipMemcpyDeviceToDevice, s));
             TRYG(sweep(ub, 0));
+            // transposes of S^o (on ub), S^e (on ua), S^o (on un), in that order
             const void* olds[3] = {ub, ua, un};
             const int pars[3] = {1, 0, 1};
             for (int j = 0; j < 3; ++j) {
                 const int p = pars[j];
-                HIPG(pm::launch_adj_targets(C.prec, olds[j], lam, w, grad, C.tab, C.sched[p], C.g, s));
-                HIPG(pm::launch_adj_duals(C.prec, lam, w, C.sched[1 - p], C.g, s));
+                if (C.win[p].npass > 0)
+                    HIPG(pm::launch_adj_win(C.prec, 0, olds[j], lam, w, gp_par[p], C.tab,
+                                            p ? 8 : 0, C.win[p], C.g, s));
+                if (C.win[1 - p].npass > 0)
+                    HIPG(pm::launch_adj_win(C.prec, 1, w, lam, nullptr, nullptr, C.tab, 0,
+                                            C.win[1 - p], C.g, s));
             }
         }
     }
+    HIPG(pm::launch_grad_sum(gpass, np0 + np1, grad, n, s));
     HIPG(pm::launch_grad_final(grad, C.tab, C.sig, C.sig + n, outg, outg + n, C.g, C.dt, s));
     if (dsa) HIPG(hipMemcpyAsync(dsa, outg, sizeof(double) * n, hipMemcpyDeviceToHost, s));
     if (dss) HIPG(hipMemcpyAsync(dss, outg + n, sizeof(double) * n, hipMemcpyDeviceToHost, s));

@@ -27,30 +27,6 @@ struct GridDesc {
     long long pstride;  // elements between consecutive moment planes
 };
 
-// One target moment of a sweep: storage slot, alpha table row, and its
-// range of entries in the entry list.
-struct SweepRow {
-    int slot;
-    int tab;
-    int begin;
-    int end;
-};
-
-// One coupling: source slot, neighbour code (0:+x 1:-x 2:+y 3:-y 4:+z 5:-z)
-// and K = s * M_d[i, j] / dx with s = +1 for a forward and -1 for a
-// backward difference, so that M_d D_d u_j = K (u_j[c + s e_d] - u_j[c]).
-struct SweepEnt {
-    int slot;
-    int nb;
-    double K;
-};
-
-struct Schedule {
-    const SweepRow* rows;
-    int nrows;
-    const SweepEnt* ents;
-};
-
 // Window sweep (see kernels.hip).  A sweep of one parity is split into
 // passes of K target degrees; pass p, source column mu (0 <= mu <= N + 1)
 // is described by host-built streams, in the order the kernel consumes them:
@@ -82,13 +58,19 @@ int win_depth(int prec);
 hipError_t launch_tables(const double* sa, const double* ss, const double* q, double* tab,
                          GridDesc g, double dt, hipStream_t st);
 
-hipError_t launch_sweep(int prec, void* u, const double* tab, Schedule s, GridDesc g,
-                        hipStream_t st);
-
 // rowbase: table row of alpha for the first target grid of the parity
 // (0 for the even sweep, 8 for an odd half step, kTabOddFull for a full one).
 hipError_t launch_sweep_win(int prec, void* u, const double* tab, int rowbase, WinArgs a,
                             GridDesc g, hipStream_t st);
+
+// Transposed substep on the window streams.  side 0 (target side): us = old
+// state, lam = cotangent (targets updated), w = output beta * lam, gp =
+// per-pass gradient rows of this parity ([npass][kGradRows][ncell], added
+// to).  side 1 (dual side): us = w, lam updated on the dual moments.
+// FP64 and FP32 only.
+hipError_t launch_adj_win(int prec, int side, const void* us, void* lam, void* w, double* gp,
+                          const double* tab, int rowbase, WinArgs a, GridDesc g, hipStream_t st);
+hipError_t launch_grad_sum(const double* gp, int nbuf, double* grad, long long n, hipStream_t st);
 
 hipError_t launch_to_f64(int prec, const void* src_plane, double* dst, long long n,
                          hipStream_t st);
@@ -103,11 +85,6 @@ hipError_t launch_check(int prec, const void* u, int nplanes, GridDesc g, double
                         unsigned long long* pcount, int npart, double* out_max,
                         unsigned long long* out_count, hipStream_t st);
 
-// Adjoint of one substep (targets = schedule `tgt`, duals = schedule `dual`).
-hipError_t launch_adj_targets(int prec, const void* uold, void* lam, void* w, double* grad,
-                              const double* tab, Schedule tgt, GridDesc g, hipStream_t st);
-hipError_t launch_adj_duals(int prec, void* lam, const void* w, Schedule dual, GridDesc g,
-                            hipStream_t st);
 hipError_t launch_grad_final(const double* grad, const double* tab, const double* sa,
                              const double* ss, double* dsa, double* dss, GridDesc g, double dt,
                              hipStream_t st);

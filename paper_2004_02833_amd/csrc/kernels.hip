@@ -184,73 +184,6 @@ hipError_t launch_tables(const double* sa, const double* ss, const double* q, do
     return hipGetLastError();
 }
 
-// ------------------------------------------------------------ gather sweep --
-// Substep S^p_tau of eq. (4)-(5) for every target moment of one parity:
-//   r_i = q_i - sum_e K_e (u_src[c + nb_e] - u_src[c]),
-//   u_i <- alpha u_i + beta r_i        (float64, rounded to the storage type)
-// Sources are the dual parity, which this launch never writes, and every
-// target reads only its own old value, so the update is in place.
-
-template <class T>
-__global__ void __launch_bounds__(256) k_sweep_gather(T* __restrict__ u,
-                                                      const double* __restrict__ tab,
-                                                      Schedule s, GridDesc g) {
-    using A = typename Acc<T>::type;
-    const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= g.ncell) return;
-    const Nbr n = neighbours(c, g);
-    for (int t = 0; t < s.nrows; ++t) {
-        const SweepRow R = s.rows[t];
-        A acc = 0;
-        for (int e = R.begin; e < R.end; ++e) {
-            const SweepEnt E = s.ents[e];
-            const T* uj = u + (long long)E.slot * g.pstride;
-            const A d = (A)ld(uj + c + pick(n, E.nb)) - (A)ld(uj + c);
-            acc += (A)E.K * d;
-        }
-        const double alpha = tab[(long long)R.tab * g.ncell + c];
-        const double beta = tab[(long long)(R.tab + 1) * g.ncell + c];
-        const double q = (R.tab == kTabMom0) ? tab[(long long)kTabQ * g.ncell + c] : 0.0;
-        T* ut = u + (long long)R.slot * g.pstride + c;
-        st(ut, alpha * (double)ld(ut) + beta * (q - (double)acc));
-    }
-}
-
-hipError_t launch_sweep(int prec, void* u, const double* tab, Schedule s, GridDesc g,
-                        hipStream_t st) {
-    const int B = 256;
-    const unsigned nb = (unsigned)((g.ncell + B - 1) / B);
-    switch (prec) {
-        case kF64:
-            hipLaunchKernelGGL(k_sweep_gather<double>, dim3(nb), dim3(B), 0, st, (double*)u, tab, s, g);
-            break;
-        case kF32:
-            hipLaunchKernelGGL(k_sweep_gather<float>, dim3(nb), dim3(B), 0, st, (float*)u, tab, s, g);
-            break;
-        default:
-            hipLaunchKernelGGL(k_sweep_gather<bf16s>, dim3(nb), dim3(B), 0, st, (bf16s*)u, tab, s, g);
-    }
-    return hipGetLastError();
-}
-
-// ------------------------------------------------------------ window sweep --
-// Same substep as k_sweep_gather, organised so that every source moment is
-// loaded once per pass (with its three one-sided neighbours) and its
-// differences are pushed straight into the partial sums of all its targets.
-//
-// Coupling structure (flux matrices in closed form): target (l, m) reads only
-// degrees l-1 and l+1; M_z keeps m, M_x keeps the cos/sin type and moves |m|
-// by one, M_y swaps the type and moves |m| by one.  A pass takes K target
-// degrees l = L0, L0+2, .., L0+2K-2 (one parity) and the K+1 source degrees
-// L0-1, .., L0+2K-1 between them, and walks the source column mu' = |m|
-// upwards.  A source in column mu' feeds target columns mu'-1 (x, y; this
-// completes them), mu' (z) and mu'+1 (x, y), so three columns of partial sums
-// are live.  A difference of source j in direction d is u_j[c + s e_d] - u_j[c]
-// with s = +1 if j is unstaggered in d and -1 otherwise; the sign and 1/dx
-// are folded into the coefficient.  Each source's four raw values for the
-// next column are requested as soon as its current ones are consumed
-// (one-column software pipeline).
-
 // ---- several consecutive x-cells per lane --------------------------------
 // A lane owns CPL consecutive cells of a row; its plane accesses are vector
 // loads/stores of CPL elements (8 to 16 bytes), so a wave moves 512 B to 1 KB
@@ -395,8 +328,21 @@ __device__ __forceinline__ long long tile_cell(const TileMap& m, long long tile,
     return (long long)x + (long long)g.nx * ((long long)y + (long long)g.ny * z);
 }
 
-template <class T, int K, int TPB, int CPL>
-__global__ void __launch_bounds__(TPB) k_sweep_win(T* __restrict__ u,
+// Finalisation modes of the window sweep:
+//   kFwd     substep of eq. (5): u_i <- alpha u_i + beta (q_i - S_i)
+//   kAdjTgt  transpose, target side: with lam_i the cotangent of the updated
+//            u_i and S_i recomputed from the old state (sources us), add
+//            lam_i u_i and lam_i (q_i - S_i) to the gradients of alpha and
+//            beta of the target's coefficient set, write w_i = beta lam_i
+//            and lam_i <- alpha lam_i
+//   kAdjDual transpose, dual side: lam_j <- lam_j + S_j with the sources
+//            read from w (the transpose of a forward difference is minus the
+//            backward one, so this is a forward-shaped stencil over w)
+enum SweepMode { kFwd = 0, kAdjTgt = 1, kAdjDual = 2 };
+
+template <class T, int K, int TPB, int CPL, int MODE>
+__global__ void __launch_bounds__(TPB) k_sweep_win(const T* __restrict__ us, T* __restrict__ u,
+                                                   T* __restrict__ uw, double* __restrict__ gp,
                                                    const double* __restrict__ tab,
                                                    const int2* __restrict__ src,
                                                    const int2* __restrict__ tgt,
@@ -404,6 +350,9 @@ __global__ void __launch_bounds__(TPB) k_sweep_win(T* __restrict__ u,
                                                    int rowbase, int N, int parity, int npass,
                                                    int per_xcd, long long ntile, TileMap tm,
                                                    GridDesc g) {
+    static_assert(MODE == kFwd || CPL == 1, "transposed sweeps use one cell per lane");
+    // the forward substep reads its sources from the state it updates
+    const T* __restrict__ sv = MODE == kFwd ? u : us;
     using A = typename Acc<T>::type;
     using V = typename Pack<T, CPL>::V;
     const int xcd = blockIdx.x % kXcds;
@@ -431,12 +380,15 @@ __global__ void __launch_bounds__(TPB) k_sweep_win(T* __restrict__ u,
     // and q (10) for the lane's cells, kept in LDS instead of registers
     __shared__ double tl[11][TPB * CPL];
     const int tid = threadIdx.x;
+    if (MODE != kAdjDual) {
 #pragma unroll
     for (int f = 0; f < 8; ++f)
 #pragma unroll
         for (int k = 0; k < CPL; ++k)
             tl[f][tid * CPL + k] = tab[(long long)(rowbase + f) * g.ncell + nb.c0 + k];
-    if (parity == 0) {
+    }
+    double ga[5] = {0, 0, 0, 0, 0}, gb[5] = {0, 0, 0, 0, 0};  // kAdjTgt gradient sums
+    if (MODE != kAdjDual && parity == 0) {
 #pragma unroll
         for (int k = 0; k < CPL; ++k) {
             tl[8][tid * CPL + k] = tab[(long long)kTabMom0 * g.ncell + nb.c0 + k];
@@ -456,7 +408,7 @@ __global__ void __launch_bounds__(TPB) k_sweep_win(T* __restrict__ u,
 #pragma unroll
     for (int b = 0; b <= K; ++b)
 #pragma unroll
-        for (int ty = 0; ty < 2; ++ty) win_fetch<T, CPL>(R[b][ty], u, sd[b * 2 + ty], nb, ps);
+        for (int ty = 0; ty < 2; ++ty) win_fetch<T, CPL>(R[b][ty], sv, sd[b * 2 + ty], nb, ps);
 #pragma unroll
     for (int w = 0; w < 3; ++w)
 #pragma unroll
@@ -491,7 +443,7 @@ __global__ void __launch_bounds__(TPB) k_sweep_win(T* __restrict__ u,
                     dy[k] = vy[k] - vc[k];
                     dz[k] = vz[k] - vc[k];
                 }
-                if (mu <= mumax) win_fetch<T, CPL>(R[b][ty], u, sdn[b * 2 + ty], nb, ps);
+                if (mu <= mumax) win_fetch<T, CPL>(R[b][ty], sv, sdn[b * 2 + ty], nb, ps);
                 if (e.x < 0) continue;
 #pragma unroll
                 for (int side = 0; side < 2; ++side) {
@@ -524,11 +476,31 @@ __global__ void __launch_bounds__(TPB) k_sweep_win(T* __restrict__ u,
                     A old[CPL];
                     unpack<T, CPL, A>(__builtin_nontemporal_load((const V*)ut), old);
                     double nv[CPL];
+                    if constexpr (MODE == kFwd) {
 #pragma unroll
-                    for (int k = 0; k < CPL; ++k) {
-                        const double q = d.y == kTabMom0 ? tl[10][tid * CPL + k] : 0.0;
-                        nv[k] = tl[ra][tid * CPL + k] * (double)old[k] +
-                                tl[ra + 1][tid * CPL + k] * (q - (double)S[0][t][ty][k]);
+                        for (int k = 0; k < CPL; ++k) {
+                            const double q = d.y == kTabMom0 ? tl[10][tid * CPL + k] : 0.0;
+                            nv[k] = tl[ra][tid * CPL + k] * (double)old[k] +
+                                    tl[ra + 1][tid * CPL + k] * (q - (double)S[0][t][ty][k]);
+                        }
+                    } else if constexpr (MODE == kAdjDual) {
+                        nv[0] = (double)old[0] + (double)S[0][t][ty][0];
+                    } else {
+                        // old[0] is lam_i; the old u_i comes from the source state
+                        const double lam = (double)old[0];
+                        const double uo = (double)ld(sv + (long long)d.x * ps + nb.c0);
+                        const double q = d.y == kTabMom0 ? tl[10][tid] : 0.0;
+                        const double r = q - (double)S[0][t][ty][0];
+                        const int set = d.y == kTabMom0 ? 4 : ((d.y >> 1) & 3);
+#pragma unroll
+                        for (int s5 = 0; s5 < 5; ++s5)
+                            if (s5 == set) {
+                                ga[s5] += lam * uo;
+                                gb[s5] += lam * r;
+                            }
+                        const double wv[1] = {tl[ra + 1][tid] * lam};
+                        if (live) st(uw + (long long)d.x * ps + nb.c0, wv[0]);
+                        nv[0] = tl[ra][tid] * lam;
                     }
                     if (live) __builtin_nontemporal_store(pack<T, CPL>(nv), (V*)ut);
                 }
@@ -544,6 +516,22 @@ __global__ void __launch_bounds__(TPB) k_sweep_win(T* __restrict__ u,
                     S[1][t][ty][k] = S[2][t][ty][k];
                     S[2][t][ty][k] = (A)0;
                 }
+    }
+    if constexpr (MODE == kAdjTgt) {
+        // gradient rows of this pass (2 s for alpha, 2 s + 1 for beta, s the
+        // coefficient set: grid order, 8 for moment 0); one workgroup owns
+        // every (pass, cell), so the accumulation needs no atomics
+        if (live) {
+            double* gq = gp + (long long)pass * kGradRows * g.ncell + nb.c0;
+            const int gbase = parity ? 4 : 0;
+#pragma unroll
+            for (int s5 = 0; s5 < 5; ++s5) {
+                if (s5 == 4 && parity != 0) continue;
+                const int row = s5 == 4 ? kTabMom0 : 2 * (gbase + s5);
+                gq[(long long)row * g.ncell] += ga[s5];
+                gq[(long long)(row + 1) * g.ncell] += gb[s5];
+            }
+        }
     }
 }
 
@@ -565,9 +553,9 @@ int win_depth(int prec) { return prec == kF64 ? PM_WIN_K64 : PM_WIN_K32; }
 #define PM_CPL16 2
 #endif
 
-template <class T, int K, int CPL>
-static void launch_win_t(T* u, const double* tab, int rowbase, WinArgs a, GridDesc g,
-                         hipStream_t st) {
+template <class T, int K, int CPL, int MODE>
+static void launch_win_t(const T* us, T* u, T* uw, double* gp, const double* tab, int rowbase,
+                         WinArgs a, GridDesc g, hipStream_t st) {
     using A = typename Acc<T>::type;
     constexpr int TPB = 256 / CPL;
     TileMap tm{0, 1, 1, 1};
@@ -584,31 +572,71 @@ static void launch_win_t(T* u, const double* tab, int rowbase, WinArgs a, GridDe
     }
     const int per_xcd = (int)((ntile + kXcds - 1) / kXcds);
     const unsigned nwg = (unsigned)((long long)kXcds * per_xcd * a.npass);
-    hipLaunchKernelGGL((k_sweep_win<T, K, TPB, CPL>), dim3(nwg), dim3(TPB), 0, st, u, tab,
-                       a.src, a.tgt, (const A*)a.coef, rowbase, a.N, a.parity, a.npass, per_xcd,
-                       ntile, tm, g);
+    hipLaunchKernelGGL((k_sweep_win<T, K, TPB, CPL, MODE>), dim3(nwg), dim3(TPB), 0, st, us, u,
+                       uw, gp, tab, a.src, a.tgt, (const A*)a.coef, rowbase, a.N, a.parity,
+                       a.npass, per_xcd, ntile, tm, g);
 }
 
 hipError_t launch_sweep_win(int prec, void* u, const double* tab, int rowbase, WinArgs a,
                             GridDesc g, hipStream_t st) {
     if (a.K != win_depth(prec)) return hipErrorInvalidValue;
     // several cells per lane need whole lane groups within every row
+#define PM_FWD(T, K, C) launch_win_t<T, K, C, kFwd>((const T*)u, (T*)u, nullptr, nullptr, tab, rowbase, a, g, st)
     if (prec == kF64) {
         if (PM_CPL64 > 1 && g.nx % PM_CPL64 == 0)
-            launch_win_t<double, PM_WIN_K64, PM_CPL64>((double*)u, tab, rowbase, a, g, st);
+            PM_FWD(double, PM_WIN_K64, PM_CPL64);
         else
-            launch_win_t<double, PM_WIN_K64, 1>((double*)u, tab, rowbase, a, g, st);
+            PM_FWD(double, PM_WIN_K64, 1);
     } else if (prec == kF32) {
         if (PM_CPL32 > 1 && g.nx % PM_CPL32 == 0)
-            launch_win_t<float, PM_WIN_K32, PM_CPL32>((float*)u, tab, rowbase, a, g, st);
+            PM_FWD(float, PM_WIN_K32, PM_CPL32);
         else
-            launch_win_t<float, PM_WIN_K32, 1>((float*)u, tab, rowbase, a, g, st);
+            PM_FWD(float, PM_WIN_K32, 1);
     } else {
         if (PM_CPL16 > 1 && g.nx % PM_CPL16 == 0)
-            launch_win_t<bf16s, PM_WIN_K32, PM_CPL16>((bf16s*)u, tab, rowbase, a, g, st);
+            PM_FWD(bf16s, PM_WIN_K32, PM_CPL16);
         else
-            launch_win_t<bf16s, PM_WIN_K32, 1>((bf16s*)u, tab, rowbase, a, g, st);
+            PM_FWD(bf16s, PM_WIN_K32, 1);
     }
+#undef PM_FWD
+    return hipGetLastError();
+}
+
+hipError_t launch_adj_win(int prec, int side, const void* us, void* lam, void* w, double* gp,
+                          const double* tab, int rowbase, WinArgs a, GridDesc g, hipStream_t st) {
+    if (a.K != win_depth(prec) || prec == kBF16) return hipErrorInvalidValue;
+    if (prec == kF64) {
+        if (side == 0)
+            launch_win_t<double, PM_WIN_K64, 1, kAdjTgt>((const double*)us, (double*)lam, (double*)w,
+                                                         gp, tab, rowbase, a, g, st);
+        else
+            launch_win_t<double, PM_WIN_K64, 1, kAdjDual>((const double*)us, (double*)lam, nullptr,
+                                                          nullptr, tab, rowbase, a, g, st);
+    } else {
+        if (side == 0)
+            launch_win_t<float, PM_WIN_K32, 1, kAdjTgt>((const float*)us, (float*)lam, (float*)w,
+                                                       gp, tab, rowbase, a, g, st);
+        else
+            launch_win_t<float, PM_WIN_K32, 1, kAdjDual>((const float*)us, (float*)lam, nullptr,
+                                                        nullptr, tab, rowbase, a, g, st);
+    }
+    return hipGetLastError();
+}
+
+// Sum of the per-pass gradient rows: grad[row][c] = sum over buffers.
+__global__ void k_grad_sum(const double* __restrict__ gp, int nbuf, double* __restrict__ grad,
+                           long long n) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (long long)kGradRows * n) return;
+    double acc = 0.0;
+    for (int b = 0; b < nbuf; ++b) acc += gp[(long long)b * kGradRows * n + i];
+    grad[i] = acc;
+}
+
+hipError_t launch_grad_sum(const double* gp, int nbuf, double* grad, long long n, hipStream_t st) {
+    const long long tot = (long long)kGradRows * n;
+    hipLaunchKernelGGL(k_grad_sum, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, gp, nbuf,
+                       grad, n);
     return hipGetLastError();
 }
 
@@ -767,103 +795,9 @@ hipError_t launch_check(int prec, const void* u, int nplanes, GridDesc g, double
 }
 
 // ----------------------------------------------------------------- adjoint --
-// Transpose of the substep u_i' = alpha_i u_i + beta_i r_i (i of parity p),
-// r_i = q_i - sum_d sum_j M_d[i,j] D_d u_j.  With cotangent lam:
-//   dL/dalpha_i += lam_i u_i,   dL/dbeta_i += lam_i r_i      (per cell)
-//   w_i = beta_i lam_i,         lam_i <- alpha_i lam_i       (k_adj_targets)
-//   lam_j += sum_d sum_i M_d[j,i] D_d^(j) w_i   (j dual)     (k_adj_duals)
-// The last line uses that the transpose of a forward periodic difference is
-// minus the backward one: the dual update has exactly the stencil of a
-// forward sweep whose targets are the dual moments, reading w as sources.
-
-template <class T>
-__global__ void __launch_bounds__(256) k_adj_targets(const T* __restrict__ uold,
-                                                     T* __restrict__ lam, T* __restrict__ w,
-                                                     double* __restrict__ grad,
-                                                     const double* __restrict__ tab, Schedule s,
-                                                     GridDesc g) {
-    using A = typename Acc<T>::type;
-    const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= g.ncell) return;
-    const Nbr n = neighbours(c, g);
-    int cur = -1;
-    double ga = 0.0, gb = 0.0;
-    for (int t = 0; t < s.nrows; ++t) {
-        const SweepRow R = s.rows[t];
-        const int set = R.tab >> 1;  // grid order, or 8 for moment 0
-        if (set != cur) {
-            if (cur >= 0) {
-                grad[(long long)(2 * cur) * g.ncell + c] += ga;
-                grad[(long long)(2 * cur + 1) * g.ncell + c] += gb;
-            }
-            cur = set;
-            ga = gb = 0.0;
-        }
-        A acc = 0;
-        for (int e = R.begin; e < R.end; ++e) {
-            const SweepEnt E = s.ents[e];
-            const T* uj = uold + (long long)E.slot * g.pstride;
-            acc += (A)E.K * ((A)ld(uj + c + pick(n, E.nb)) - (A)ld(uj + c));
-        }
-        const double alpha = tab[(long long)R.tab * g.ncell + c];
-        const double beta = tab[(long long)(R.tab + 1) * g.ncell + c];
-        const double q = (R.tab == kTabMom0) ? tab[(long long)kTabQ * g.ncell + c] : 0.0;
-        const long long o = (long long)R.slot * g.pstride + c;
-        const double l = (double)ld(lam + o);
-        ga += l * (double)ld(uold + o);
-        gb += l * (q - (double)acc);
-        st(w + o, beta * l);
-        st(lam + o, alpha * l);
-    }
-    if (cur >= 0) {
-        grad[(long long)(2 * cur) * g.ncell + c] += ga;
-        grad[(long long)(2 * cur + 1) * g.ncell + c] += gb;
-    }
-}
-
-template <class T>
-__global__ void __launch_bounds__(256) k_adj_duals(T* __restrict__ lam, const T* __restrict__ w,
-                                                   Schedule s, GridDesc g) {
-    using A = typename Acc<T>::type;
-    const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= g.ncell) return;
-    const Nbr n = neighbours(c, g);
-    for (int t = 0; t < s.nrows; ++t) {
-        const SweepRow R = s.rows[t];
-        A acc = 0;
-        for (int e = R.begin; e < R.end; ++e) {
-            const SweepEnt E = s.ents[e];
-            const T* wj = w + (long long)E.slot * g.pstride;
-            acc += (A)E.K * ((A)ld(wj + c + pick(n, E.nb)) - (A)ld(wj + c));
-        }
-        T* lt = lam + (long long)R.slot * g.pstride + c;
-        st(lt, (double)ld(lt) + (double)acc);
-    }
-}
-
-hipError_t launch_adj_targets(int prec, const void* uold, void* lam, void* w, double* grad,
-                              const double* tab, Schedule s, GridDesc g, hipStream_t st) {
-    const unsigned nb = (unsigned)((g.ncell + 255) / 256);
-    if (prec == kF64)
-        hipLaunchKernelGGL(k_adj_targets<double>, dim3(nb), dim3(256), 0, st, (const double*)uold, (double*)lam, (double*)w, grad, tab, s, g);
-    else if (prec == kF32)
-        hipLaunchKernelGGL(k_adj_targets<float>, dim3(nb), dim3(256), 0, st, (const float*)uold, (float*)lam, (float*)w, grad, tab, s, g);
-    else
-        hipLaunchKernelGGL(k_adj_targets<bf16s>, dim3(nb), dim3(256), 0, st, (const bf16s*)uold, (bf16s*)lam, (bf16s*)w, grad, tab, s, g);
-    return hipGetLastError();
-}
-
-hipError_t launch_adj_duals(int prec, void* lam, const void* w, Schedule s, GridDesc g,
-                            hipStream_t st) {
-    const unsigned nb = (unsigned)((g.ncell + 255) / 256);
-    if (prec == kF64)
-        hipLaunchKernelGGL(k_adj_duals<double>, dim3(nb), dim3(256), 0, st, (double*)lam, (const double*)w, s, g);
-    else if (prec == kF32)
-        hipLaunchKernelGGL(k_adj_duals<float>, dim3(nb), dim3(256), 0, st, (float*)lam, (const float*)w, s, g);
-    else
-        hipLaunchKernelGGL(k_adj_duals<bf16s>, dim3(nb), dim3(256), 0, st, (bf16s*)lam, (const bf16s*)w, s, g);
-    return hipGetLastError();
-}
+// The transposed substeps run on the window sweep (modes kAdjTgt/kAdjDual
+// above); what remains is the chain rule from the decay factors to the
+// cell-centred medium.
 
 // d beta / d c for beta = (1 - exp(-c tau))/c:  -tau^2 F(c tau) with
 // F(z) = (1 - (1+z) e^{-z}) / z^2 = sum_k (-1)^k (k+1) z^k / (k+2)!,
