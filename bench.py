@@ -112,7 +112,14 @@ def run_gpu(pm, w, prec, steps, warmup, keep_state=False):
         times["three_sweep_s"] = t3 - t2
         state = None
         if keep_state:
-            state = [pm.pm_read(i) for i in state_moments(w)]
+            # sampled moments, and on very large grids every k-th cell of them
+            buf = torch.empty(w.shape, dtype=torch.float64, device=dev)
+            stride = max(1, w.n ** 3 // (1 << 22))
+            state = []
+            for i in state_moments(w):
+                pm.pm_read_dev(i, buf.data_ptr())
+                state.append(buf.reshape(-1)[::stride].cpu().numpy())
+            del buf
         maxabs, nonfinite = pm.pm_check()
         return t1 - t0, times, state, (maxabs, nonfinite)
     finally:
@@ -145,8 +152,9 @@ def copy_ceiling(gib):
 
 
 def state_moments(w):
-    """Moments read back for the FP32-vs-FP64 comparison: all of them on grids
-    up to ~1e9 values, an evenly spaced sample of 100 beyond (host memory)."""
+    """Moments read back for the comparison between forms: all of them on
+    grids up to ~1e9 values, an evenly spaced sample of 100 beyond (host
+    memory; there every k-th cell is kept as well, see run_gpu)."""
     if w.n ** 3 * w.V <= 1_000_000_000:
         return list(range(w.V))
     return sorted(set(np.linspace(0, w.V - 1, 100).astype(int).tolist()))
@@ -214,6 +222,8 @@ def main():
     ap.add_argument("--workload", default="p39_smooth")
     ap.add_argument("--cpu-steps", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--forms", default="fp64,fp32",
+                    help="storage forms to time; the first is the headline value")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--bf16", action="store_true", help="also time the BF16-storage probe")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the gradient timing")
@@ -235,41 +245,37 @@ def main():
     say = lambda *a: print(*a, file=sys.stderr, flush=True)
 
     copy = copy_ceiling(args.copy_gib) if args.copy_gib > 0 else None
-    say("bench: %s P%d %d^3, fp64, %d warmup + %d steps" % (w.name, w.N, w.n, args.warmup, args.steps))
-    t64, times64, s64, chk64 = run_gpu(pm, w, pm.PM_FP64, args.steps, args.warmup,
-                                       keep_state=not args.no_fp32 or args.bf16)
-    value = ncell * V * args.steps / t64 / 1e9
-    roof = roofline(w.N, ncell, 8, times64)
-    roof["traffic"] = measured_traffic("sweep_odd", w.name, "f64")
-
-    fp32 = None
-    if not args.no_fp32:
-        say("bench: fp32")
-        t32, times32, s32, chk32 = run_gpu(pm, w, pm.PM_FP32, args.steps, args.warmup,
-                                           keep_state=True)
-        num = max(float(np.abs(a - b).max()) for a, b in zip(s32, s64))
-        den = max(float(np.abs(b).max()) for b in s64)
-        r32 = roofline(w.N, ncell, 4, times32)
-        r32["traffic"] = measured_traffic("sweep_odd", w.name, "f32")
-        fp32 = {"value": round(ncell * V * args.steps / t32 / 1e9, 3),
-                "ms_per_step": round(t32 / args.steps * 1e3, 4),
-                "three_sweep_value": round(ncell * V * args.steps / times32["three_sweep_s"] / 1e9, 3),
-                "rel_err_vs_fp64_gpu": num / den, "moments_compared": len(s64),
-                "roofline": r32}
-        del s32
-
-    bf16 = None
-    if args.bf16:
-        say("bench: bf16 storage probe")
-        tb, timesb, sb, chkb = run_gpu(pm, w, pm.PM_BF16, args.steps, args.warmup,
-                                       keep_state=s64 is not None)
-        rb = roofline(w.N, ncell, 2, timesb)
-        bf16 = {"value": round(ncell * V * args.steps / tb / 1e9, 3),
-                "ms_per_step": round(tb / args.steps * 1e3, 4), "roofline": rb}
-        if s64 is not None:
-            bf16["rel_err_vs_fp64_gpu"] = (max(float(np.abs(a - b).max()) for a, b in zip(sb, s64))
-                                           / max(float(np.abs(b).max()) for b in s64))
-        del sb
+    forms = [f.strip() for f in args.forms.split(",") if f.strip()]
+    if args.no_fp32 and "fp32" in forms:
+        forms.remove("fp32")
+    if args.bf16 and "bf16" not in forms:
+        forms.append("bf16")
+    PREC = {"fp64": (pm.PM_FP64, 8, "f64"), "fp32": (pm.PM_FP32, 4, "f32"), "bf16": (pm.PM_BF16, 2, "bf16")}
+    results = {}
+    ref_state = None
+    for k, form in enumerate(forms):
+        prec, esz, dname = PREC[form]
+        say("bench: %s P%d %d^3, %s, %d warmup + %d steps" % (w.name, w.N, w.n, form, args.warmup, args.steps))
+        keep = len(forms) > 1
+        t, times, state, chk = run_gpu(pm, w, prec, args.steps, args.warmup, keep_state=keep)
+        r = roofline(w.N, ncell, esz, times)
+        r["traffic"] = measured_traffic("sweep_odd", w.name, dname)
+        res = {"value": round(ncell * V * args.steps / t / 1e9, 3), "ms_per_step": round(t / args.steps * 1e3, 4),
+               "three_sweep": {"value": round(ncell * V * args.steps / times["three_sweep_s"] / 1e9, 3),
+                               "ms_per_step": round(times["three_sweep_s"] / args.steps * 1e3, 4)},
+               "dtype": dname, "roofline": r, "state_check": {"max_abs": chk[0], "nonfinite": chk[1]},
+               "sweep_ms": {"odd": times["odd"], "even": times["even"]}}
+        if k == 0:
+            ref_state = state
+        elif state is not None and ref_state is not None:
+            res["rel_err_vs_%s_gpu" % forms[0]] = (
+                max(float(np.abs(a - b).max()) for a, b in zip(state, ref_state))
+                / max(float(np.abs(b).max()) for b in ref_state))
+            res["moments_compared"] = len(state)
+        results[form] = res
+        del state
+    del ref_state
+    head = results[forms[0]]
 
     adjoint = None
     if not args.no_adjoint:
@@ -285,31 +291,31 @@ def main():
 
     out = {
         "metric": "GDoF-updates/s (cell x moment per step) P39 3D; % HBM peak; FP32 vs FP64 error",
-        "value": round(value, 3),
+        "value": head["value"],
         "unit": "GDoF-updates/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(t64 / args.steps * 1e3, 4),
+        "ms_per_step": head["ms_per_step"],
         "schedule": "merged odd half steps: 2n+1 sweep launches per pm_step(n)",
-        "three_sweep": {"value": round(ncell * V * args.steps / times64["three_sweep_s"] / 1e9, 3),
-                        "ms_per_step": round(times64["three_sweep_s"] / args.steps * 1e3, 4)},
+        "three_sweep": head["three_sweep"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": head["dtype"],
         "data": "synthetic",
         "config": {"workload": "%s: P%d (%d moments), %d^3 periodic cells, dx=1/%d, dt=dx/2"
                                % (w.name, w.N, V, w.n, w.n),
                    "cells": ncell, "moments": V, "seed": w.seed},
-        "roofline": roof,
-        "fp32": fp32,
-        "bf16": bf16,
+        "roofline": head["roofline"],
+        "forms": {f: r for f, r in results.items() if f != forms[0]},
         "adjoint": adjoint,
         "cpu_baseline": cpu,
+        "paper_context": "139.1 MLCUP/s = 0.139 GDoF-updates/s per core, P39 FP64, Haswell Xeon "
+                         "E5-2623 v3 (kasper), optimised AVX2 sweeps; other machine, context only",
         "copy_ceiling": copy,
-        "state_check": {"max_abs": chk64[0], "nonfinite": chk64[1]},
-        "sweep_ms": {"odd": times64["odd"], "even": times64["even"]},
+        "state_check": head["state_check"],
+        "sweep_ms": head["sweep_ms"],
     }
     print(json.dumps(out), flush=True)
 

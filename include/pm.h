@@ -71,6 +71,15 @@ int pm_set_precision(int precision);
 int pm_init(int N, int nx, int ny, int nz, double dx, double dt,
             const double* sigma_a, const double* sigma_s, const double* q);
 
+/* Same for rectangular cells of edges dx x dy x dz (Sec. 2.1: the box is
+ * divided into equal cells of size dx x dy x dz).  A d-difference is divided
+ * by its own edge; the stability limit becomes
+ * 1 / (lambda_max(N) sqrt(1/dx^2 + 1/dy^2 + 1/dz^2)).  pm_init(..., dx, ...)
+ * is pm_init_cells(..., dx, dx, dx, ...).  Staggered points sit at
+ * ((x + 1/2 + ox/2) dx, (y + 1/2 + oy/2) dy, (z + 1/2 + oz/2) dz). */
+int pm_init_cells(int N, int nx, int ny, int nz, double dx, double dy, double dz, double dt,
+                  const double* sigma_a, const double* sigma_s, const double* q);
+
 /* Set moment `moment` (canonical index) from a host float64 array at its
  * staggered points (initial data psi(0, x, Omega), Sec. 2, eq. (1)).
  * Rounds to the storage precision.  Clears a gradient recording (it restarts

@@ -17,7 +17,7 @@ PM_OK, PM_EINVAL, PM_ENOMEM, PM_EDEVICE, PM_ESTATE, PM_ENONFINITE = 0, -1, -2, -
 PM_FP64, PM_FP32, PM_BF16 = 0, 1, 2
 PM_N_MAX = 63
 
-EXPORTED = ("pm_set_precision", "pm_init", "pm_write", "pm_write_dev", "pm_step", "pm_set_merge",
+EXPORTED = ("pm_set_precision", "pm_init", "pm_init_cells", "pm_write", "pm_write_dev", "pm_step", "pm_set_merge",
             "pm_read",
             "pm_read_dev", "pm_set_checkpoint", "pm_grad", "pm_total", "pm_check",
             "pm_bind_stream", "pm_sync", "pm_cfl_warning", "pm_timing", "pm_sweep_times",
@@ -50,6 +50,7 @@ def lib():
         sig = {
             "pm_set_precision": ([i32], i32),
             "pm_init": ([i32, i32, i32, i32, f64, f64, P(f64), P(f64), P(f64)], i32),
+            "pm_init_cells": ([i32, i32, i32, i32, f64, f64, f64, f64, P(f64), P(f64), P(f64)], i32),
             "pm_write": ([i32, P(f64)], i32),
             "pm_write_dev": ([i32, vp], i32),
             "pm_step": ([i32], i32),
@@ -118,6 +119,25 @@ def pm_init(N, nx, ny, nz, dx, dt, sigma_a, sigma_s, q=None):
     qq = None if q is None else fld(q, "q")
     rc = lib().pm_init(int(N), int(nx), int(ny), int(nz), float(dx), float(dt), _dptr(sa),
                        _dptr(ss), None if qq is None else _dptr(qq))
+    _check(rc)
+    _shape = (int(nz), int(ny), int(nx))
+    _V = (int(N) + 1) ** 2
+    return rc
+
+
+def pm_init_cells(N, nx, ny, nz, dx, dy, dz, dt, sigma_a, sigma_s, q=None):
+    """pm_init for rectangular dx x dy x dz cells."""
+    global _shape, _V
+    n = int(nx) * int(ny) * int(nz)
+    if min(int(nx), int(ny), int(nz)) < 1:
+        n = -1
+    fld = (lambda a, name: _field(a, n, name)) if n > 0 else (
+        lambda a, name: np.ascontiguousarray(a, dtype=np.float64).reshape(-1))
+    sa = fld(sigma_a, "sigma_a")
+    ss = fld(sigma_s, "sigma_s")
+    qq = None if q is None else fld(q, "q")
+    rc = lib().pm_init_cells(int(N), int(nx), int(ny), int(nz), float(dx), float(dy), float(dz),
+                             float(dt), _dptr(sa), _dptr(ss), None if qq is None else _dptr(qq))
     _check(rc)
     _shape = (int(nz), int(ny), int(nx))
     _V = (int(N) + 1) ** 2

@@ -47,7 +47,8 @@ struct Ctx {
     bool live = false;
     int N = 0, V = 0, nx = 0, ny = 0, nz = 0;
     long long ncell = 0;
-    double dx = 0, dt = 0;
+    double h[3] = {0, 0, 0};  // cell edges dx, dy, dz
+    double dt = 0;
     int prec = PM_FP64;
     size_t esz = 8;
     pm::GridDesc g{};
@@ -205,7 +206,7 @@ int build_window_tables() {
                                 if (it == flux.end()) continue;
                                 const double sgn = ((bits >> dir[r]) & 1) ? -1.0 : 1.0;
                                 h.coef[((((size_t)(pass * MU1 + mu) * (K + 1) + b) * 2 + ty) * 2 + side) * 5 + r] =
-                                    sgn * it->second / C.dx;
+                                    sgn * it->second / C.h[dir[r]];
                                 ++used;
                             }
                         }
@@ -326,11 +327,18 @@ int pm_set_precision(int p) {
 
 int pm_init(int N, int nx, int ny, int nz, double dx, double dt, const double* sigma_a,
             const double* sigma_s, const double* q) {
+    return pm_init_cells(N, nx, ny, nz, dx, dx, dx, dt, sigma_a, sigma_s, q);
+}
+
+int pm_init_cells(int N, int nx, int ny, int nz, double dx, double dy, double dz, double dt,
+                  const double* sigma_a, const double* sigma_s, const double* q) {
     if (N < 0 || N > PM_N_MAX) return fail(PM_EINVAL, "N must be in [0, 63]");
     if (nx < 1 || ny < 1 || nz < 1) return fail(PM_EINVAL, "grid sizes must be >= 1");
     const long long ncell = (long long)nx * ny * nz;
     if (ncell >= (1LL << 31)) return fail(PM_EINVAL, "more than 2^31 - 1 cells");
-    if (!(dx > 0.0) || !std::isfinite(dx)) return fail(PM_EINVAL, "dx must be positive and finite");
+    for (double hd : {dx, dy, dz})
+        if (!(hd > 0.0) || !std::isfinite(hd))
+            return fail(PM_EINVAL, "cell edges dx, dy, dz must be positive and finite");
     if (!(dt > 0.0) || !std::isfinite(dt)) return fail(PM_EINVAL, "dt must be positive and finite");
     if (!sigma_a || !sigma_s) return fail(PM_EINVAL, "sigma_a and sigma_s are required");
     std::string msg;
@@ -347,7 +355,9 @@ int pm_init(int N, int nx, int ny, int nz, double dx, double dt, const double* s
     C.ny = ny;
     C.nz = nz;
     C.ncell = ncell;
-    C.dx = dx;
+    C.h[0] = dx;
+    C.h[1] = dy;
+    C.h[2] = dz;
     C.dt = dt;
     C.prec = g_pending_prec;
     C.esz = elem_size(C.prec);
@@ -357,7 +367,10 @@ int pm_init(int N, int nx, int ny, int nz, double dx, double dt, const double* s
     C.g.ncell = ncell;
     C.g.pstride = plane_stride(ncell);
     C.L = pm::make_layout(N);
-    const double lim = N > 0 ? dx / (std::sqrt(3.0) * pm::lambda_max(N)) : INFINITY;
+    // sigma = 0 Fourier symbol: stable iff dt * lambda_max * sqrt(sum_d 1/h_d^2) <= 1
+    const double lim =
+        N > 0 ? 1.0 / (pm::lambda_max(N) * std::sqrt(1.0 / (dx * dx) + 1.0 / (dy * dy) + 1.0 / (dz * dz)))
+              : INFINITY;
     C.cfl_warn = dt > lim ? 1 : 0;
 
     int rc;

@@ -87,3 +87,13 @@ def test_p7_lattice_128_cubed():
     w = workloads.p7_lattice()
     corners = [(58, 58, 58), (50, 60, 66)]
     check(w, (pm.PM_FP64, pm.PM_FP32), 8, corners)
+
+
+def test_reactor_500_cubed_p19():
+    """Reactor-vessel stand-in, P19 at 500^3 (5e10 unknowns: 200 GB in FP32,
+    100 GB in BF16; rows of 500 cells use linear tiles): blocks across a rod
+    lattice and the core edge."""
+    w = workloads.reactor()
+    n = w.n
+    corners = [(n // 2 - 4, n // 4 - 4, n // 4 - 4), (n // 2, n // 2, n // 2 + 3)]
+    check(w, (pm.PM_FP32, pm.PM_BF16), 2, corners)

@@ -263,3 +263,24 @@ def test_bf16_and_fp32_small_shapes(shape):
     say("small %s fp32 %.2e bf16 %.2e" % (shape, e32, e16))
     assert e32 <= FP32_TOL
     assert e16 <= 2e-2
+
+
+@pytest.mark.parametrize("N,shape,h", [(3, (4, 5, 6), (0.2, 0.13, 0.31)), (7, (3, 4, 64), (1 / 64, 1 / 48, 1 / 80)),
+                                       (5, (2, 3, 160), (0.01, 0.02, 0.015))])
+def test_rectangular_cells(N, shape, h):
+    """dx x dy x dz cells through pm_init_cells against the oracle (FP64 and FP32)."""
+    sa, ss, q, u = rand_problem(N, shape, 41)
+    dt = 0.3 * min(h)
+    ref = st.run(st.Setup(N, shape, h, dt, sa, ss, q), u, 4)
+    for prec, tol in ((pm.PM_FP64, 1e-13), (pm.PM_FP32, FP32_TOL)):
+        nz, ny, nx = shape
+        pm.pm_set_precision(prec)
+        pm.pm_init_cells(N, nx, ny, nz, h[0], h[1], h[2], dt, sa, ss, q)
+        try:
+            for i in range((N + 1) ** 2):
+                pm.pm_write(i, u[i])
+            pm.pm_step(4)
+            got = np.stack([pm.pm_read(i) for i in range((N + 1) ** 2)])
+        finally:
+            pm.pm_finalize()
+        assert relerr(got, ref) <= tol, prec

@@ -80,6 +80,10 @@ def test_validation_before_device():
         with pytest.raises(pm.PmError) as e:
             pm.pm_init(*args)
         assert e.value.code == pm.PM_EINVAL
+    for hs in ((0.5, 0.0, 0.5), (0.5, 0.5, -1.0), (float("inf"), 0.5, 0.5)):
+        with pytest.raises(pm.PmError) as e:
+            pm.pm_init_cells(3, 2, 2, 2, *hs, 0.1, ok, ok)
+        assert e.value.code == pm.PM_EINVAL
     with pytest.raises(pm.PmError) as e:
         pm.pm_init(3, 2, 2, 2, 0.5, 0.1, ok, ok, np.full(8, np.nan))
     assert e.value.code == pm.PM_EINVAL

@@ -489,3 +489,53 @@ def test_dbeta_series_continuity():
     ref = np.array([(st.E(-(cc + 1e-7) * tau) * tau - st.E(-(cc - 1e-7) * tau) * tau)[()] / 2e-7
                     for cc in c[1:]])
     assert np.allclose(d[1:], ref, rtol=1e-6)
+
+
+def test_rectangular_cells_fourier_and_dense():
+    """Rectangular dx x dy x dz cells (Sec. 2.1): the array stepping agrees with
+    the dense assembly and a plane wave evolves by the symbol with per-direction
+    difference symbols 2 i sin(k_d h_d / 2) / h_d."""
+    N, shape = 3, (5, 4, 6)
+    h = (1.0 / 6, 1.0 / 4 * 0.7, 1.0 / 5 * 1.3)
+    dt = 0.3 * min(h)
+    rng = np.random.default_rng(60)
+    sa = np.full(shape, 0.25)
+    ss = np.full(shape, 0.6)
+    s = st.Setup(N, shape, h, dt, sa, ss)
+    L = (shape[2] * h[0], shape[1] * h[1], shape[0] * h[2])
+    k = 2 * np.pi * np.array([1.0 / L[0], -1.0 / L[1], 2.0 / L[2]])
+    uh = rng.normal(size=16) + 1j * rng.normal(size=16)
+    ph = np.empty((16,) + shape, dtype=complex)
+    for i in range(16):
+        x, y, z = dense.staggered_positions(shape, h, s.o[i])
+        ph[i] = np.exp(1j * (k[0] * x + k[1] * y + k[2] * z))
+    G = dense.fourier_symbol(N, k, h, dt, 0.25, 0.85)
+    want = ((np.linalg.matrix_power(G, 4) @ uh)[:, None, None, None] * ph).real
+    assert np.abs(st.run(s, (uh[:, None, None, None] * ph).real, 4) - want).max() < 1e-13 * np.abs(want).max()
+    sr = st.Setup(N, shape, h, dt, rng.uniform(0, .5, shape), rng.uniform(0, 1, shape), rng.uniform(0, 1, shape))
+    u = rng.normal(size=(16,) + shape)
+    S, b = dense.step_matrix(sr)
+    x = u.ravel().copy()
+    for _ in range(2):
+        x = S @ x + b
+    assert np.abs(x - st.run(sr, u, 2).ravel()).max() <= 1e-13 * np.abs(x).max()
+
+
+def test_cfl_limit_rectangular_cells():
+    """sigma = 0 with unequal edges: stable iff dt <= 1/(lambda_max sqrt(sum 1/h_d^2))."""
+    N = 3
+    h = (1.0, 0.6, 1.7)
+    lam = np.polynomial.legendre.leggauss(N + 1)[0].max()
+    lim = 1.0 / (lam * np.sqrt(sum(1.0 / v ** 2 for v in h)))
+    ks = np.linspace(0, np.pi, 5)
+    def radius(dt):
+        r = 0.0
+        for a in ks:
+            for b in ks:
+                for c in ks:
+                    kv = (a / h[0], b / h[1], c / h[2])
+                    G = dense.fourier_symbol(N, kv, h, dt, 0.0, 0.0)
+                    r = max(r, np.abs(np.linalg.eigvals(G)).max())
+        return r
+    assert radius(0.98 * lim) <= 1 + 1e-10
+    assert radius(1.05 * lim) > 1 + 1e-6

@@ -16,6 +16,7 @@ geometry, so these recipes stand in for them.
   p39_smooth   P39, 64^3, 100 steps: smooth random medium, 3 pulses + noise
   p39_large    the p39_smooth recipe at 160^3, 50 steps
   p7_adjoint   P7, 64^3, 200 steps, checkpoints every 20: gradient workload
+  reactor      P19, 500^3: stand-in for the reactor-vessel showcase
 """
 from dataclasses import dataclass, field
 from typing import Callable, Optional
@@ -209,10 +210,46 @@ def p7_adjoint(seed=3, n=64, N=7, nsteps=200, checkpoint=20):
     return w
 
 
+def reactor(seed=4, n=500, N=19, nsteps=20, name="reactor"):
+    """Stand-in for the reactor-vessel showcase: a cube of n^3 cells of
+    0.2 cm (n = 500: 1 m) with an outer concrete shell, a water box and a
+    core of vertical fuel rods 5 cells (1 cm) thick.  Printed: rods 1 cm
+    thick, q0 = 2, Sigma_a = 10 in water and 5 in concrete, Sigma_s = 1.
+    Not printed (readings): concrete shell 10 % of the edge on every side,
+    core = the central 50 % of the edge in x and y and 70 % in z, square rod
+    lattice with a pitch of 3 rod widths, rods with Sigma_a = 0 and the
+    source q = 2, Sigma_s = 1 everywhere, initial state zero.  `seed` only
+    shifts the rod lattice by up to one pitch."""
+    rng = np.random.default_rng(seed)
+    c = np.arange(n)
+    shell = max(1, int(round(0.1 * n)))
+    rod = max(1, int(round(n / 100)))            # 1 cm on a 1 m box
+    pitch = 3 * rod
+    off = int(rng.integers(0, pitch))
+    core_xy = (c >= n // 4) & (c < n - n // 4)
+    core_z = (c >= int(0.15 * n)) & (c < n - int(0.15 * n))
+    in_rod = ((c - n // 4 + off) % pitch) < rod
+    z, y, x = np.meshgrid(c, c, c, indexing="ij", sparse=True)
+    concrete = ((x < shell) | (x >= n - shell) | (y < shell) | (y >= n - shell) |
+                (z < shell) | (z >= n - shell))
+    rods = core_xy[x] & core_xy[y] & core_z[z] & in_rod[x] & in_rod[y]
+    sa = np.where(concrete, 5.0, np.where(rods, 0.0, 10.0))
+    ss = np.ones((n, n, n))
+    q = np.where(rods & ~concrete, 2.0, 0.0)
+
+    def moment(i):
+        return np.zeros((n, n, n))
+
+    w = Workload(name, N, n, nsteps, sa, ss, q, moment, seed,
+                 extra={"rod": rod, "pitch": pitch, "shell": shell, "offset": off})
+    return w
+
+
 RECIPES = {
     "p3_pulse": p3_pulse,
     "p7_lattice": p7_lattice,
     "p39_smooth": p39_smooth,
     "p39_large": p39_large,
     "p7_adjoint": p7_adjoint,
+    "reactor": reactor,
 }
