@@ -95,5 +95,10 @@ def test_reactor_500_cubed_p19():
     lattice and the core edge."""
     w = workloads.reactor()
     n = w.n
-    corners = [(n // 2 - 4, n // 4 - 4, n // 4 - 4), (n // 2, n // 2, n // 2 + 3)]
+    q = w.q
+    # blocks centred on a rod cell: mid-core, and straddling the core's top face
+    rods = np.nonzero(q[n // 2, :, n // 2 - 10:n // 2 + 10] > 0)
+    y0, x0 = int(rods[0][len(rods[0]) // 2]), int(rods[1][0]) + n // 2 - 10
+    ztop = int(np.nonzero(q[:, y0, x0] > 0)[0].max())
+    corners = [(n // 2 - 4, y0 - 4, x0 - 4), (ztop - 3, y0 - 2, x0 - 5)]
     check(w, (pm.PM_FP32, pm.PM_BF16), 2, corners)
