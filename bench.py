@@ -48,7 +48,7 @@ def kernel_source_hash():
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_2004_02833_amd", "csrc")
     for name in sorted(os.listdir(d)):
-        if name.endswith((".hip", ".h")):
+        if name.endswith((".hip", ".h")) and name != "probe.hip":
             h.update(open(os.path.join(d, name), "rb").read())
     return h.hexdigest()[:16]
 
@@ -160,6 +160,21 @@ def state_moments(w):
     return sorted(set(np.linspace(0, w.V - 1, 100).astype(int).tolist()))
 
 
+def ceilings(ncell):
+    """Measured bandwidth ceilings (libpm_probe.so): flat read, flat copy and
+    a pure-memory kernel with the sweeps' access pattern, in GB/s."""
+    import ctypes
+    lib = ctypes.CDLL(os.path.join(ROOT, "paper_2004_02833_amd", "libpm_probe.so"))
+    lib.pmp_ceilings.argtypes = [ctypes.c_longlong, ctypes.c_longlong, ctypes.POINTER(ctypes.c_double)]
+    out = (ctypes.c_double * 4)()
+    rc = lib.pmp_ceilings(2 << 30, (ncell // 256) * 256, out)
+    if rc != 0:
+        return {"error": rc}
+    return {"flat_read": round(out[0], 1), "flat_copy": round(out[1], 1),
+            "sweep_pattern_f64": round(out[2], 1), "sweep_pattern_f32": round(out[3], 1),
+            "unit": "GB/s"}
+
+
 def roofline(N, ncell, esz, times):
     n_odd, ms_odd = times["odd"]
     per_launch = ms_odd / max(n_odd, 1) / 1e3
@@ -227,6 +242,8 @@ def main():
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--bf16", action="store_true", help="also time the BF16-storage probe")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the gradient timing")
+    ap.add_argument("--no-ceilings", action="store_true",
+                    help="skip the bandwidth ceilings (libpm_probe.so)")
     ap.add_argument("--copy-gib", type=float, default=2.0,
                     help="size of the calibration copy (0: skip)")
     args = ap.parse_args()
@@ -245,6 +262,7 @@ def main():
     say = lambda *a: print(*a, file=sys.stderr, flush=True)
 
     copy = copy_ceiling(args.copy_gib) if args.copy_gib > 0 else None
+    ceil = None if args.no_ceilings else ceilings(min(ncell, 262144))
     forms = [f.strip() for f in args.forms.split(",") if f.strip()]
     if args.no_fp32 and "fp32" in forms:
         forms.remove("fp32")
@@ -314,6 +332,7 @@ def main():
         "paper_context": "139.1 MLCUP/s = 0.139 GDoF-updates/s per core, P39 FP64, Haswell Xeon "
                          "E5-2623 v3 (kasper), optimised AVX2 sweeps; other machine, context only",
         "copy_ceiling": copy,
+        "ceilings": ceil,
         "state_check": head["state_check"],
         "sweep_ms": head["sweep_ms"],
     }

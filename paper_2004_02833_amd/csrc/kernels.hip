@@ -404,6 +404,18 @@ __global__ void __launch_bounds__(TPB) k_sweep_win(const T* __restrict__ us, T* 
     const A* cf = coef + (long long)pass * MU1 * (K + 1) * 20;
 
     Raw<T, CPL> R[K + 1][2];  // raw values of the current source column
+    // forward sweep: old values of the targets finished in the next column,
+    // requested one column ahead (transposed modes read theirs in place)
+    typename Pack<T, CPL>::V tpf[K][2];
+    if constexpr (MODE == kFwd) {
+#pragma unroll
+        for (int t = 0; t < K; ++t)
+#pragma unroll
+            for (int ty = 0; ty < 2; ++ty) {
+                const int2 dn = td[t * 2 + ty];
+                tpf[t][ty] = dn.x >= 0 ? __builtin_nontemporal_load((const V*)(u + (long long)dn.x * ps + nb.c0)) : V{};
+            }
+    }
     A S[3][K][2][CPL];        // partial sums: target columns mu-1, mu, mu+1
 #pragma unroll
     for (int b = 0; b <= K; ++b)
@@ -465,6 +477,25 @@ __global__ void __launch_bounds__(TPB) k_sweep_win(const T* __restrict__ us, T* 
         // column mu-1 is complete: u <- alpha u + beta (q - sum)
         if (mu >= 1) {
             const int2* tdc = td + (mu - 1) * K * 2;
+            typename Pack<T, CPL>::V tcur[K][2];
+            if constexpr (MODE == kFwd) {
+#pragma unroll
+                for (int t = 0; t < K; ++t)
+#pragma unroll
+                    for (int ty = 0; ty < 2; ++ty) tcur[t][ty] = tpf[t][ty];
+                if (mu <= mumax) {
+                    const int2* tdn = td + mu * K * 2;
+#pragma unroll
+                    for (int t = 0; t < K; ++t)
+#pragma unroll
+                        for (int ty = 0; ty < 2; ++ty) {
+                            const int2 dn = tdn[t * 2 + ty];
+                            if (dn.x >= 0)
+                                tpf[t][ty] = __builtin_nontemporal_load(
+                                    (const V*)(u + (long long)dn.x * ps + nb.c0));
+                        }
+                }
+            }
 #pragma unroll
             for (int t = 0; t < K; ++t) {
 #pragma unroll
@@ -474,7 +505,10 @@ __global__ void __launch_bounds__(TPB) k_sweep_win(const T* __restrict__ us, T* 
                     const int ra = d.y == kTabMom0 ? 8 : 2 * ((d.y >> 1) & 3);
                     T* ut = u + (long long)d.x * ps + nb.c0;
                     A old[CPL];
-                    unpack<T, CPL, A>(__builtin_nontemporal_load((const V*)ut), old);
+                    if constexpr (MODE == kFwd)
+                        unpack<T, CPL, A>(tcur[t][ty], old);
+                    else
+                        unpack<T, CPL, A>(__builtin_nontemporal_load((const V*)ut), old);
                     double nv[CPL];
                     if constexpr (MODE == kFwd) {
 #pragma unroll
