@@ -9,8 +9,9 @@ the transposed map applied to a cotangent lam (of u') is
     lam_j     += - sum_i sum_d M_d[i,j] D_d^T (beta_i lam_i)     (j dual)
     lam_i      = alpha_i lam_i
 with D_d^T the matrix transpose of the periodic one-sided difference.  The
-coefficients depend on the medium through c = mean of (sigma_a [+ sigma_s])
-over the cells sharing a point:
+coefficients depend on the medium through c = mean of
+sigma_a + (1 - g_l) sigma_s over the cells sharing a point (g_0 = 1; g_l = 0
+for l >= 1 with isotropic scattering):
     d alpha/dc = -tau alpha,   d beta/dc = (tau alpha - beta)/c  (-> -tau^2/2).
 Loss: L = 1/2 sum_cells (u_0(T) - target)^2, no cell-volume weight.
 """
@@ -95,6 +96,5 @@ def loss_and_grad(s, u0, nsteps, target):
     for i in range(s.V):
         g = staggered_mean_T(gc[i], s.o[i])
         ga += g
-        if i > 0:
-            gs += g
+        gs += (1.0 - s.g[s.ell[i]]) * g
     return L, ga, gs, lam

@@ -10,6 +10,7 @@ import subprocess
 import numpy as np
 
 from . import basis
+from .stepper import scattering_moments
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "pn_oracle.c")
@@ -34,7 +35,7 @@ def lib():
         P = ctypes.POINTER
         i32, f64 = ctypes.c_int, ctypes.c_double
         common = [i32, i32, i32, i32, f64, f64, f64, f64, P(i32), i32, P(i32), P(i32), P(i32),
-                  P(f64), P(f64), P(f64), P(f64)]
+                  P(f64), P(f64), P(f64), P(f64), P(f64)]
         L.pno_run.argtypes = common + [P(f64), i32, i32]
         L.pno_run.restype = i32
         L.pno_grad.argtypes = common + [P(f64), i32, i32, P(f64), P(f64), P(f64), i32]
@@ -72,7 +73,7 @@ def _p(a, t):
     return a.ctypes.data_as(ctypes.POINTER(t))
 
 
-def _args(T, shape, h, dt, sa, ss, q):
+def _args(T, shape, h, dt, sa, ss, q, scattering=None):
     nz, ny, nx = shape
     hx, hy, hz = (h, h, h) if np.isscalar(h) else h
     i32, f64 = ctypes.c_int, ctypes.c_double
@@ -80,29 +81,32 @@ def _args(T, shape, h, dt, sa, ss, q):
     ss = np.ascontiguousarray(ss, dtype=np.float64).reshape(-1)
     q = (np.zeros(nx * ny * nz) if q is None
          else np.ascontiguousarray(q, dtype=np.float64).reshape(-1))
-    keep = (sa, ss, q)
+    gl = None if scattering is None else np.ascontiguousarray(scattering_moments(T.N, scattering))
+    keep = (sa, ss, q, gl)
     return keep, [T.V, nx, ny, nz, hx, hy, hz, dt, _p(T.o, i32), int(T.ti.size), _p(T.ti, i32),
-                  _p(T.sj, i32), _p(T.dr, i32), _p(T.vv, f64), _p(sa, f64), _p(ss, f64), _p(q, f64)]
+                  _p(T.sj, i32), _p(T.dr, i32), _p(T.vv, f64), _p(sa, f64), _p(ss, f64), _p(q, f64),
+                  None if gl is None else _p(gl, f64)]
 
 
-def run(N, shape, h, dt, sa, ss, q, u0, nsteps, threads=0):
-    """Moments after nsteps literal Strang steps; u0 of shape (V, nz, ny, nx)."""
+def run(N, shape, h, dt, sa, ss, q, u0, nsteps, threads=0, scattering=None):
+    """Moments after nsteps literal Strang steps; u0 of shape (V, nz, ny, nx).
+    scattering: g_l for l = 1, 2, ... (None: isotropic)."""
     T = Tables(N)
     u = np.array(u0, dtype=np.float64, order="C", copy=True).reshape((T.V,) + tuple(shape))
-    keep, a = _args(T, shape, h, dt, sa, ss, q)
+    keep, a = _args(T, shape, h, dt, sa, ss, q, scattering)
     lib().pno_run(*a, _p(u, ctypes.c_double), int(nsteps), int(threads))
     del keep
     return u
 
 
-def grad(N, shape, h, dt, sa, ss, q, u0, nsteps, ck, target, threads=0):
+def grad(N, shape, h, dt, sa, ss, q, u0, nsteps, ck, target, threads=0, scattering=None):
     """(L, dL/dsigma_a, dL/dsigma_s) for L = 1/2 ||u_0(T) - target||^2."""
     T = Tables(N)
     u = np.ascontiguousarray(u0, dtype=np.float64).reshape((T.V,) + tuple(shape))
     tg = np.ascontiguousarray(target, dtype=np.float64).reshape(-1)
     dsa = np.zeros(tg.size)
     dss = np.zeros(tg.size)
-    keep, a = _args(T, shape, h, dt, sa, ss, q)
+    keep, a = _args(T, shape, h, dt, sa, ss, q, scattering)
     L = lib().pno_grad(*a, _p(u, ctypes.c_double), int(nsteps), int(ck), _p(tg, ctypes.c_double),
                        _p(dsa, ctypes.c_double), _p(dss, ctypes.c_double), int(threads))
     del keep

@@ -73,12 +73,14 @@ def step_matrix(s):
     return S, b
 
 
-def fourier_symbol(N, k, h, dt, c0, c1):
+def fourier_symbol(N, k, h, dt, c0, c1, c_deg=None):
     """V x V amplification matrix of one step for a homogeneous medium.
 
     k: wave vector (kx, ky, kz); h: (hx, hy, hz); c0 = coefficient of the
-    zeroth moment, c1 = coefficient of all l >= 1 moments; no source.
-    Amplitudes are referred to each moment's own staggered points.
+    zeroth moment, c1 = coefficient of all l >= 1 moments; c_deg, when
+    given, replaces both with one coefficient per degree l = 0..N
+    (anisotropic scattering); no source.  Amplitudes are referred to each
+    moment's own staggered points.
     """
     Mx, My, Mz = basis.flux_matrices(N)
     o = basis.reflection_parities(N)
@@ -88,6 +90,8 @@ def fourier_symbol(N, k, h, dt, c0, c1):
     L = kappa[0] * Mx + kappa[1] * My + kappa[2] * Mz
     c = np.full(V, float(c1))
     c[0] = c0
+    if c_deg is not None:
+        c = np.array([float(c_deg[basis.lm_of(i)[0]]) for i in range(V)])
 
     def sub(p, tau):
         A = np.eye(V, dtype=complex)

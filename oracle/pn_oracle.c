@@ -15,7 +15,10 @@
  *     E(0) = 1;
  *   - eq. (6): odd half step, even full step, odd half step.
  * c = sigma_a for moment 0 and sigma_a + sigma_s otherwise, averaged over the
- * cells that share a staggered point; q acts on moment 0 only.
+ * cells that share a staggered point; q acts on moment 0 only.  With
+ * anisotropic scattering (per-degree moments g_l of a phase function, g_0 = 1)
+ * moment i of degree l >= 1 uses c = sigma_a + (1 - g_l) sigma_s instead,
+ * averaged the same way; its field is formed per moment when it is updated.
  *
  * The flux matrices and the parities come in as arguments (the Python oracle
  * computes them by quadrature and by evaluating reflections).
@@ -41,6 +44,10 @@ typedef struct {
     const double *q;
     double *cbar[9];         /* coefficient set k: 0..7 family, 8 = moment 0 */
     double *Eodd[9], *Eeven[9];
+    const double *sa, *ss;
+    const double *gl;        /* NULL (isotropic) or g_0..g_N */
+    int *deg;                /* degree l of moment i */
+    double *work;            /* one coefficient field (anisotropic case) */
 } prob_t;
 
 static int fam_of(const int *o) { return o[0] + 2 * o[1] + 4 * o[2]; }
@@ -73,13 +80,20 @@ static void stagger_mean(const prob_t *P, const double *f, const int *o, double 
 
 static int setup(prob_t *P, int V, int nx, int ny, int nz, double hx, double hy, double hz,
                  double dt, const int *o, int nnz, const int *ti, const int *sj, const int *dir,
-                 const double *val, const double *sa, const double *ss, const double *q) {
+                 const double *val, const double *sa, const double *ss, const double *q,
+                 const double *gl) {
     memset(P, 0, sizeof *P);
     P->V = V; P->nx = nx; P->ny = ny; P->nz = nz;
     P->ncell = (long)nx * ny * nz;
     P->h[0] = hx; P->h[1] = hy; P->h[2] = hz; P->dt = dt;
-    P->o = o; P->q = q;
+    P->o = o; P->q = q; P->sa = sa; P->ss = ss; P->gl = gl;
     if (V <= 0 || nx <= 0 || ny <= 0 || nz <= 0) return -1;
+    P->deg = malloc(sizeof(int) * V);
+    for (int i = 0, l = 0; i < V; ++i) {
+        while ((l + 1) * (l + 1) <= i) ++l;
+        P->deg[i] = l;
+    }
+    P->work = gl ? malloc(sizeof(double) * P->ncell) : NULL;
     P->rp = calloc((size_t)V + 1, sizeof(int));
     P->cj = malloc(sizeof(int) * (nnz > 0 ? nnz : 1));
     P->cd = malloc(sizeof(int) * (nnz > 0 ? nnz : 1));
@@ -114,6 +128,19 @@ static int setup(prob_t *P, int V, int nx, int ny, int nz, double hx, double hy,
 static void teardown(prob_t *P) {
     free(P->rp); free(P->cj); free(P->cd); free(P->cv);
     for (int k = 0; k < 9; ++k) { free(P->cbar[k]); free(P->Eodd[k]); free(P->Eeven[k]); }
+    free(P->deg); free(P->work);
+}
+
+/* Coefficient field of moment i on its own points (anisotropic case):
+ * the staggered mean of sigma_a + (1 - g_l) sigma_s (sigma_a for i = 0),
+ * written to P->work. */
+static const double *aniso_cbar(const prob_t *P, int i) {
+    double *f = malloc(sizeof(double) * P->ncell);
+    const double w = 1.0 - P->gl[P->deg[i]];
+    for (long c = 0; c < P->ncell; ++c) f[c] = i == 0 ? P->sa[c] : P->sa[c] + w * P->ss[c];
+    stagger_mean(P, f, P->o + 3 * i, P->work);
+    free(f);
+    return P->work;
 }
 
 /* r_i at cell (x,y,z): q_i - sum M_d[i,j] D_d u_j */
@@ -140,8 +167,8 @@ static void substep(const prob_t *P, double *u, int parity, double tau, int even
         const int *oi = P->o + 3 * i;
         if (((oi[0] + oi[1] + oi[2]) & 1) != parity) continue;
         int k = cset(P, i);
-        const double *cb = P->cbar[k];
-        const double *Ek = even_tau ? P->Eeven[k] : P->Eodd[k];
+        const double *cb = P->gl ? aniso_cbar(P, i) : P->cbar[k];
+        const double *Ek = P->gl ? NULL : even_tau ? P->Eeven[k] : P->Eodd[k];
         double *ui = u + (long)i * P->ncell;
 #pragma omp parallel for schedule(static)
         for (int z = 0; z < P->nz; ++z)
@@ -149,7 +176,8 @@ static void substep(const prob_t *P, double *u, int parity, double tau, int even
                 for (int x = 0; x < P->nx; ++x) {
                     long c = cell(P, x, y, z);
                     double r = residual(P, u, i, x, y, z);
-                    ui[c] = ui[c] + tau * (r - cb[c] * ui[c]) * Ek[c];
+                    double E = Ek ? Ek[c] : Efun(-cb[c] * tau);
+                    ui[c] = ui[c] + tau * (r - cb[c] * ui[c]) * E;
                 }
     }
 }
@@ -160,15 +188,16 @@ static void full_step(const prob_t *P, double *u) {
     substep(P, u, 1, 0.5 * P->dt, 0);
 }
 
+/* gl: NULL for isotropic scattering, else g_0..g_N (g_0 = 1). */
 int pno_run(int V, int nx, int ny, int nz, double hx, double hy, double hz, double dt,
             const int *o, int nnz, const int *ti, const int *sj, const int *dir, const double *val,
-            const double *sa, const double *ss, const double *q, double *u, int nsteps,
-            int nthreads) {
+            const double *sa, const double *ss, const double *q, const double *gl, double *u,
+            int nsteps, int nthreads) {
 #ifdef _OPENMP
     if (nthreads > 0) omp_set_num_threads(nthreads);
 #endif
     prob_t P;
-    if (setup(&P, V, nx, ny, nz, hx, hy, hz, dt, o, nnz, ti, sj, dir, val, sa, ss, q)) return -1;
+    if (setup(&P, V, nx, ny, nz, hx, hy, hz, dt, o, nnz, ti, sj, dir, val, sa, ss, q, gl)) return -1;
     for (int s = 0; s < nsteps; ++s) full_step(&P, u);
     teardown(&P);
     return 0;
@@ -190,7 +219,9 @@ int pno_threads(void) {
 
 /* ---------------- adjoint ----------------
  * Transpose of one substep with targets i of the given parity:
- *   gc_k  += lam_i (u_i d alpha/dc + r_i d beta/dc)   (k = coefficient set of i)
+ *   gc_k  += lam_i (u_i d alpha/dc + r_i d beta/dc)   (k = coefficient set of i;
+ *            anisotropic case: k = family of i into the sigma_a sums and,
+ *            weighted by 1 - g_l, into the sigma_s sums gc[9 + family])
  *   lam_j += - sum M_d[i,j] D_d^T (beta_i lam_i)      (j dual)
  *   lam_i  = alpha_i lam_i
  * with alpha = exp(-c tau), beta = tau E(-c tau).  D^T of the forward
@@ -211,10 +242,12 @@ static void substep_T(const prob_t *P, const double *u_old, double *lam, int par
         const int *oi = P->o + 3 * i;
         if (((oi[0] + oi[1] + oi[2]) & 1) != parity) continue;
         int k = cset(P, i);
-        const double *cb = P->cbar[k];
+        const double *cb = P->gl ? aniso_cbar(P, i) : P->cbar[k];
         const double *ui = u_old + (long)i * n;
         double *li = lam + (long)i * n;
-        double *g = gc[k];
+        double *g = P->gl ? gc[fam_of(oi)] : gc[k];
+        double *gs = P->gl ? gc[9 + fam_of(oi)] : NULL;
+        const double ws = P->gl ? 1.0 - P->gl[P->deg[i]] : 0.0;
 #pragma omp parallel for schedule(static)
         for (int z = 0; z < P->nz; ++z)
             for (int y = 0; y < P->ny; ++y)
@@ -223,7 +256,9 @@ static void substep_T(const prob_t *P, const double *u_old, double *lam, int par
                     double cc = cb[c];
                     double a = exp(-cc * tau), b = tau * Efun(-cc * tau);
                     double r = residual(P, u_old, i, x, y, z);
-                    g[c] += li[c] * (ui[c] * (-tau * a) + r * dbeta(cc, tau));
+                    double gcv = li[c] * (ui[c] * (-tau * a) + r * dbeta(cc, tau));
+                    g[c] += gcv;
+                    if (gs && i != 0) gs[c] += ws * gcv;
                     w[c] = b * li[c];
                 }
         for (int kk = P->rp[i]; kk < P->rp[i + 1]; ++kk) {
@@ -256,13 +291,13 @@ static void substep_T(const prob_t *P, const double *u_old, double *lam, int par
 double pno_grad(int V, int nx, int ny, int nz, double hx, double hy, double hz, double dt,
                 const int *o, int nnz, const int *ti, const int *sj, const int *dir,
                 const double *val, const double *sa, const double *ss, const double *q,
-                const double *u0, int nsteps, int ck, const double *target, double *dsa,
-                double *dss, int nthreads) {
+                const double *gl, const double *u0, int nsteps, int ck, const double *target,
+                double *dsa, double *dss, int nthreads) {
 #ifdef _OPENMP
     if (nthreads > 0) omp_set_num_threads(nthreads);
 #endif
     prob_t P;
-    if (setup(&P, V, nx, ny, nz, hx, hy, hz, dt, o, nnz, ti, sj, dir, val, sa, ss, q)) return NAN;
+    if (setup(&P, V, nx, ny, nz, hx, hy, hz, dt, o, nnz, ti, sj, dir, val, sa, ss, q, gl)) return NAN;
     long n = P.ncell, sz = (long)V * n;
     if (ck < 1) ck = 1;
     int nseg = (nsteps + ck - 1) / ck;
@@ -276,8 +311,8 @@ double pno_grad(int V, int nx, int ny, int nz, double hx, double hy, double hz, 
     double L = 0.0;
     double *lam = calloc(sz, sizeof(double));
     for (long c = 0; c < n; ++c) { double d = u[c] - target[c]; L += 0.5 * d * d; lam[c] = d; }
-    double *gc[9];
-    for (int k = 0; k < 9; ++k) gc[k] = calloc(n, sizeof(double));
+    double *gc[17];  /* sets 0..8; anisotropic case: 0..7 sigma_a and 9..16 sigma_s sums */
+    for (int k = 0; k < 17; ++k) gc[k] = calloc(n, sizeof(double));
     double *seg = malloc(sizeof(double) * sz * ck);
     double *ua = malloc(sizeof(double) * sz), *ub = malloc(sizeof(double) * sz);
     for (int g = nseg - 1; g >= 0; --g) {
@@ -309,17 +344,19 @@ double pno_grad(int V, int nx, int ny, int nz, double hx, double hy, double hz, 
         for (int z = 0; z < nz; ++z)
             for (int y = 0; y < ny; ++y)
                 for (int x = 0; x < nx; ++x) {
-                    double gv = gc[k][cell(&P, x, y, z)] * wgt;
+                    long cc = cell(&P, x, y, z);
+                    double gv = gc[k][cc] * wgt;
+                    double gsv = (gl ? (k < 8 ? gc[9 + k][cc] : 0.0) : (k != 8 ? gc[k][cc] : 0.0)) * wgt;
                     for (int bz = 0; bz <= ok[2]; ++bz)
                         for (int by = 0; by <= ok[1]; ++by)
                             for (int bx = 0; bx <= ok[0]; ++bx) {
                                 long t = cell(&P, wrap(x + bx, nx), wrap(y + by, ny), wrap(z + bz, nz));
                                 dsa[t] += gv;
-                                if (k != 8) dss[t] += gv;
+                                dss[t] += gsv;
                             }
                 }
     }
-    for (int k = 0; k < 9; ++k) free(gc[k]);
+    for (int k = 0; k < 17; ++k) free(gc[k]);
     free(cp); free(u); free(lam); free(seg); free(ua); free(ub);
     teardown(&P);
     return L;

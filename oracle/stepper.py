@@ -19,6 +19,15 @@ Medium (Sec. 2, eq. (2) and Sec. 3.2): c = sigma_a for the zeroth moment and
 sigma_a + sigma_s for l >= 1 (isotropic scattering); q enters only the zeroth
 moment.  Coefficients on staggered points are the arithmetic mean of c over
 the 2, 4 or 8 cells that share the point.
+
+Anisotropic scattering (Sec. 2, the slab moment equations): a scattering
+kernel that depends only on the angle between the directions acts on degree
+l through its Legendre moment Sigma_sl, so the collision coefficient of
+degree l is Sigma_a + Sigma_s0 - Sigma_sl.  With Sigma_sl = g_l sigma_s
+(g_0 = 1; g_l the moments of a fixed phase function) this is
+    c_l = sigma_a + (1 - g_l) sigma_s,
+which gives sigma_a for l = 0 and the isotropic case for g_l = 0 (l >= 1).
+The same staggered mean is taken of c_l.
 """
 import numpy as np
 
@@ -39,7 +48,9 @@ def E(z):
 class Setup:
     """Everything the literal step needs, derived from the paper's definitions."""
 
-    def __init__(self, N, shape, h, dt, sigma_a, sigma_s, q=None):
+    def __init__(self, N, shape, h, dt, sigma_a, sigma_s, q=None, scattering=None):
+        """scattering: g_l for l = 1, 2, ... (None: isotropic; degrees past
+        the sequence and past N are isotropic / unused)."""
         self.N = N
         self.V = basis.n_moments(N)
         self.shape = tuple(shape)            # (nz, ny, nx)
@@ -54,15 +65,27 @@ class Setup:
         self.sigma_a, self.sigma_s = sa, ss
         self.q = (np.zeros(self.shape) if q is None
                   else np.asarray(q, dtype=np.float64).reshape(self.shape))
+        self.g = scattering_moments(N, scattering)
         self.cbar = []
         for i in range(self.V):
-            c = sa if i == 0 else sa + ss
+            c = sa if i == 0 else sa + (1.0 - self.g[self.ell[i]]) * ss
             self.cbar.append(staggered_mean(c, self.o[i]))
         self.targets = {p: [i for i in range(self.V) if self.parity[i] == p] for p in (0, 1)}
         self.sources = {}
         for i in range(self.V):
             self.sources[i] = [(d, j, self.M[d][i, j]) for d in range(3)
                                for j in np.nonzero(self.M[d][i])[0]]
+
+
+def scattering_moments(N, scattering):
+    """g_0 .. g_N: g_0 = 1, then the given g_l for l >= 1, zero past them."""
+    g = np.zeros(N + 1)
+    g[0] = 1.0
+    if scattering is not None:
+        vals = np.asarray(scattering, dtype=np.float64).ravel()
+        k = min(N, vals.size)
+        g[1:k + 1] = vals[:k]
+    return g
 
 
 def staggered_mean(c, o):
