@@ -84,7 +84,9 @@ def run_gpu(pm, w, prec, steps, warmup, keep_state=False):
     dev = torch.device("cuda", 0)
     pm.pm_set_precision(prec)
     pm.pm_bind_stream(torch.cuda.current_stream(dev).cuda_stream)
+    pm.pm_set_scattering(w.extra.get("scattering"))
     pm.pm_init(w.N, n, n, n, w.h, w.dt, w.sigma_a, w.sigma_s, w.q)
+    pm.pm_set_scattering(None)
     try:
         for i in range(w.V):
             plane = w.moment_device(i, dev)
@@ -221,7 +223,8 @@ def cpu_baseline(w, steps):
     u0 = w.initial()
     threads = c_oracle.threads()
     t0 = time.perf_counter()
-    c_oracle.run(w.N, w.shape, w.h, w.dt, w.sigma_a, w.sigma_s, w.q, u0, steps)
+    c_oracle.run(w.N, w.shape, w.h, w.dt, w.sigma_a, w.sigma_s, w.q, u0, steps,
+                 scattering=w.extra.get("scattering"))
     dt = time.perf_counter() - t0
     return {"value": round(w.n ** 3 * w.V * steps / dt / 1e9, 5), "unit": "GDoF-updates/s",
             "cores": threads, "kind": "oracle",

@@ -25,9 +25,9 @@
  *     with the box [0, nx dx) x [0, ny dx) x [0, nz dx).  Moment 0 (the
  *     radiative intensity) is on the cell centres (grid G111).
  *   - Medium: coefficient sigma_a for moment 0 and sigma_a + sigma_s for
- *     l >= 1 (isotropic scattering, eq. (2)); q feeds moment 0 only.  On a
- *     staggered point the coefficient is the mean over the 2, 4 or 8 cells
- *     sharing the point.
+ *     l >= 1 (isotropic scattering, eq. (2); per-degree coefficients with
+ *     pm_set_scattering); q feeds moment 0 only.  On a staggered point the
+ *     coefficient is the mean over the 2, 4 or 8 cells sharing the point.
  *   - One global context, not thread-safe.  The library copies every input
  *     and never keeps a caller pointer; it owns all device memory it uses.
  *   - All int-returning calls give PM_OK (0) on success and a negative code
@@ -58,6 +58,24 @@ extern "C" {
  * factors exp(-c tau) and tau E(-c tau) are always kept in float64.
  * Returns PM_EINVAL for an unknown value. */
 int pm_set_precision(int precision);
+
+/* Anisotropic scattering for the next pm_init / pm_init_cells (default:
+ * isotropic).  The collision coefficient of degree l is
+ *     c_l = sigma_a + (1 - g_l) sigma_s,   g_0 = 1,
+ * i.e. Sigma_tl = Sigma_a + Sigma_s0 - Sigma_sl with Sigma_sl = g_l sigma_s
+ * (Sec. 2, the moment equations: a scattering kernel that depends only on
+ * the angle between directions acts on degree l through its l-th Legendre
+ * moment).  g[l - 1] holds g_l for l = 1..count; degrees above count use
+ * g_l = 0 (the isotropic value, c_l = sigma_a + sigma_s).  Example:
+ * Henyey-Greenstein with asymmetry a has g_l = a^l.  count = 0 (g may be
+ * NULL) restores isotropic scattering.  On staggered points c_l is the mean
+ * over the cells sharing the point, as for isotropic scattering.  When some
+ * g_l != 0 (1 <= l <= N) the sweeps form per-degree decay factors (more
+ * arithmetic per cell, the same memory traffic); pm_grad then also
+ * differentiates through the (1 - g_l) weights.  The library copies g.
+ * Errors: PM_EINVAL (count outside [0, PM_N_MAX], a value not finite or
+ * outside [-1, 1]); the setting is then unchanged. */
+int pm_set_scattering(const double* g, int count);
 
 /* Create the context (replacing a live one): moment order N (0..PM_N_MAX),
  * grid nx, ny, nz >= 1, cell edge dx > 0, time step dt > 0, host arrays

@@ -17,7 +17,7 @@ PM_OK, PM_EINVAL, PM_ENOMEM, PM_EDEVICE, PM_ESTATE, PM_ENONFINITE = 0, -1, -2, -
 PM_FP64, PM_FP32, PM_BF16 = 0, 1, 2
 PM_N_MAX = 63
 
-EXPORTED = ("pm_set_precision", "pm_init", "pm_init_cells", "pm_write", "pm_write_dev", "pm_step", "pm_set_merge",
+EXPORTED = ("pm_set_precision", "pm_set_scattering", "pm_init", "pm_init_cells", "pm_write", "pm_write_dev", "pm_step", "pm_set_merge",
             "pm_read",
             "pm_read_dev", "pm_set_checkpoint", "pm_grad", "pm_total", "pm_check",
             "pm_bind_stream", "pm_sync", "pm_cfl_warning", "pm_timing", "pm_sweep_times",
@@ -49,6 +49,7 @@ def lib():
         vp = ctypes.c_void_p
         sig = {
             "pm_set_precision": ([i32], i32),
+            "pm_set_scattering": ([P(f64), i32], i32),
             "pm_init": ([i32, i32, i32, i32, f64, f64, P(f64), P(f64), P(f64)], i32),
             "pm_init_cells": ([i32, i32, i32, i32, f64, f64, f64, f64, P(f64), P(f64), P(f64)], i32),
             "pm_write": ([i32, P(f64)], i32),
@@ -105,6 +106,16 @@ def pm_last_error():
 
 def pm_set_precision(precision):
     return _check(lib().pm_set_precision(int(precision)))
+
+
+def pm_set_scattering(g=None):
+    """Per-degree scattering moments g_1, g_2, ... for the next pm_init
+    (None or empty: isotropic)."""
+    if g is None or len(g) == 0:
+        return _check(lib().pm_set_scattering(None, 0))
+    arr = np.ascontiguousarray(np.asarray(g, dtype=np.float64).ravel())
+    return _check(lib().pm_set_scattering(arr.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                          int(arr.size)))
 
 
 def pm_init(N, nx, ny, nz, dx, dt, sigma_a, sigma_s, q=None):

@@ -25,6 +25,7 @@ namespace {
 
 std::string g_err = "no error";
 int g_pending_prec = PM_FP64;
+std::vector<double> g_pending_scat;  // g_1, g_2, ... for the next pm_init
 int g_merge = 1;
 hipStream_t g_bound = nullptr;  // caller's stream (nullptr: own stream)
 
@@ -56,6 +57,8 @@ struct Ctx {
     void* u = nullptr;
     double* tab = nullptr;
     double* sig = nullptr;  // sigma_a, sigma_s (device copies)
+    bool aniso = false;     // some g_l != 0 for 1 <= l <= N
+    double* gl = nullptr;   // g_0 .. g_N on the device (anisotropic scattering)
     void* win_mem = nullptr;  // window sweep streams (both parities)
     pm::WinArgs win[2]{};
     double* plane64 = nullptr;
@@ -122,6 +125,7 @@ void release() {
     dfree(C.u);
     dfree(C.tab);
     dfree(C.sig);
+    dfree(C.gl);
     dfree(C.win_mem);
     dfree(C.plane64);
     dfree(C.red);
@@ -267,8 +271,10 @@ int sweep(void* u, int parity, bool full = false) {
         HIPCHK(hipEventCreate(&b));
         HIPCHK(hipEventRecord(a, C.stream()));
     }
-    const int rowbase = parity == 0 ? 0 : full ? pm::kTabOddFull : 8;
-    HIPCHK(pm::launch_sweep_win(C.prec, u, C.tab, rowbase, C.win[parity], C.g, C.stream()));
+    const double tau = parity == 0 || full ? C.dt : 0.5 * C.dt;
+    const int rowbase = parity == 0 ? 0 : full && !C.aniso ? pm::kTabOddFull : 8;
+    const pm::Aniso an{C.aniso ? C.gl : nullptr, tau};
+    HIPCHK(pm::launch_sweep_win(C.prec, u, C.tab, rowbase, an, C.win[parity], C.g, C.stream()));
     if (C.timing) {
         HIPCHK(hipEventRecord(b, C.stream()));
         C.ev[parity].push_back({a, b});
@@ -325,6 +331,18 @@ int pm_set_precision(int p) {
     return PM_OK;
 }
 
+int pm_set_scattering(const double* g, int count) {
+    if (count < 0 || count > PM_N_MAX)
+        return fail(PM_EINVAL, "scattering count must be in [0, " + std::to_string(PM_N_MAX) + "]");
+    if (count > 0 && !g) return fail(PM_EINVAL, "scattering moments are NULL");
+    for (int l = 0; l < count; ++l)
+        if (!std::isfinite(g[l]) || g[l] < -1.0 || g[l] > 1.0)
+            return fail(PM_EINVAL, "g[" + std::to_string(l) + "] (degree " + std::to_string(l + 1) +
+                                       ") is not finite or outside [-1, 1]");
+    g_pending_scat.assign(g, g + count);
+    return PM_OK;
+}
+
 int pm_init(int N, int nx, int ny, int nz, double dx, double dt, const double* sigma_a,
             const double* sigma_s, const double* q) {
     return pm_init_cells(N, nx, ny, nz, dx, dx, dx, dt, sigma_a, sigma_s, q);
@@ -367,6 +385,10 @@ int pm_init_cells(int N, int nx, int ny, int nz, double dx, double dy, double dz
     C.g.ncell = ncell;
     C.g.pstride = plane_stride(ncell);
     C.L = pm::make_layout(N);
+    std::vector<double> gl(N + 1, 0.0);
+    gl[0] = 1.0;
+    for (int l = 1; l <= N && l - 1 < (int)g_pending_scat.size(); ++l) gl[l] = g_pending_scat[l - 1];
+    C.aniso = std::any_of(gl.begin() + 1, gl.end(), [](double v) { return v != 0.0; });
     // sigma = 0 Fourier symbol: stable iff dt * lambda_max * sqrt(sum_d 1/h_d^2) <= 1
     const double lim =
         N > 0 ? 1.0 / (pm::lambda_max(N) * std::sqrt(1.0 / (dx * dx) + 1.0 / (dy * dy) + 1.0 / (dz * dz)))
@@ -405,6 +427,7 @@ int pm_init_cells(int N, int nx, int ny, int nz, double dx, double dy, double dz
     TRY(dmalloc(&C.u, C.state_bytes(), "state"));
     TRY(dmalloc(&C.tab, sizeof(double) * pm::kTabRows * (size_t)ncell, "tables"));
     TRY(dmalloc(&C.sig, sizeof(double) * 2 * (size_t)ncell, "sigma"));
+    if (C.aniso) TRY(dmalloc(&C.gl, sizeof(double) * gl.size(), "scattering moments"));
     TRY(dmalloc(&C.plane64, sizeof(double) * (size_t)ncell, "plane"));
     TRY(dmalloc(&C.red, sizeof(double) * (C.npart + 1), "reduction"));
     TRY(dmalloc(&C.redc, sizeof(unsigned long long) * (C.npart + 1), "reduction"));
@@ -417,7 +440,11 @@ int pm_init_cells(int N, int nx, int ny, int nz, double dx, double dy, double dz
     TRY(dev(hipMemcpyAsync(C.sig, sigma_a, sizeof(double) * ncell, hipMemcpyHostToDevice, s), "copy sigma_a"));
     TRY(dev(hipMemcpyAsync(C.sig + ncell, sigma_s, sizeof(double) * ncell, hipMemcpyHostToDevice, s), "copy sigma_s"));
     if (q) TRY(dev(hipMemcpyAsync(C.plane64, q, sizeof(double) * ncell, hipMemcpyHostToDevice, s), "copy q"));
-    TRY(dev(pm::launch_tables(C.sig, C.sig + ncell, q ? C.plane64 : nullptr, C.tab, C.g, dt, s), "tables"));
+    if (C.aniso)
+        TRY(dev(hipMemcpyAsync(C.gl, gl.data(), sizeof(double) * gl.size(), hipMemcpyHostToDevice, s),
+                "copy scattering moments"));
+    TRY(dev(pm::launch_tables(C.sig, C.sig + ncell, q ? C.plane64 : nullptr, C.tab, C.g, dt, C.aniso, s),
+            "tables"));
     TRY(dev(pm::launch_fill_zero(C.u, (long long)C.state_bytes(), s), "zero state"));
     TRY(dev(hipStreamSynchronize(s), "sync"));
 #undef TRY
@@ -604,17 +631,18 @@ int pm_grad(const double* dL_du0, double* dsa, double* dss) {
             const int pars[3] = {1, 0, 1};
             for (int j = 0; j < 3; ++j) {
                 const int p = pars[j];
+                const pm::Aniso an{C.aniso ? C.gl : nullptr, p ? 0.5 * C.dt : C.dt};
                 if (C.win[p].npass > 0)
                     HIPG(pm::launch_adj_win(C.prec, 0, olds[j], lam, w, gp_par[p], C.tab,
-                                            p ? 8 : 0, C.win[p], C.g, s));
+                                            p ? 8 : 0, an, C.win[p], C.g, s));
                 if (C.win[1 - p].npass > 0)
-                    HIPG(pm::launch_adj_win(C.prec, 1, w, lam, nullptr, nullptr, C.tab, 0,
+                    HIPG(pm::launch_adj_win(C.prec, 1, w, lam, nullptr, nullptr, C.tab, 0, an,
                                             C.win[1 - p], C.g, s));
             }
         }
     }
     HIPG(pm::launch_grad_sum(gpass, np0 + np1, grad, n, s));
-    HIPG(pm::launch_grad_final(grad, C.tab, C.sig, C.sig + n, outg, outg + n, C.g, C.dt, s));
+    HIPG(pm::launch_grad_final(grad, C.tab, C.sig, C.sig + n, outg, outg + n, C.g, C.dt, C.aniso, s));
     if (dsa) HIPG(hipMemcpyAsync(dsa, outg, sizeof(double) * n, hipMemcpyDeviceToHost, s));
     if (dss) HIPG(hipMemcpyAsync(dss, outg + n, sizeof(double) * n, hipMemcpyDeviceToHost, s));
     HIPG(hipStreamSynchronize(s));

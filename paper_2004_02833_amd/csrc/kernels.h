@@ -55,21 +55,33 @@ struct WinArgs {
 // Target degrees per pass used for a storage precision.
 int win_depth(int prec);
 
+// Anisotropic scattering: gl = device array of g_0 .. g_N (g_0 = 1), or
+// nullptr for the isotropic tables; tau = length of the substep.
+struct Aniso {
+    const double* gl;
+    double tau;
+};
+
+// aniso: rows 2s, 2s + 1 hold the means of sigma_a and sigma_s on grid s
+// (s in storage order) and row kTabQ holds q; the other rows are unused.
 hipError_t launch_tables(const double* sa, const double* ss, const double* q, double* tab,
-                         GridDesc g, double dt, hipStream_t st);
+                         GridDesc g, double dt, bool aniso, hipStream_t st);
 
 // rowbase: table row of alpha for the first target grid of the parity
-// (0 for the even sweep, 8 for an odd half step, kTabOddFull for a full one).
-hipError_t launch_sweep_win(int prec, void* u, const double* tab, int rowbase, WinArgs a,
-                            GridDesc g, hipStream_t st);
+// (0 for the even sweep, 8 for an odd half step, kTabOddFull for a full one;
+// with anisotropic scattering 0 or 8, the substep length coming from an.tau).
+hipError_t launch_sweep_win(int prec, void* u, const double* tab, int rowbase, Aniso an,
+                            WinArgs a, GridDesc g, hipStream_t st);
 
 // Transposed substep on the window streams.  side 0 (target side): us = old
 // state, lam = cotangent (targets updated), w = output beta * lam, gp =
 // per-pass gradient rows of this parity ([npass][kGradRows][ncell], added
 // to).  side 1 (dual side): us = w, lam updated on the dual moments.
-// FP64 and FP32 only.
+// FP64 and FP32 only.  With anisotropic scattering the gradient rows 2s and
+// 2s + 1 are dL/d(mean sigma_a) and dL/d(mean sigma_s) of grid s.
 hipError_t launch_adj_win(int prec, int side, const void* us, void* lam, void* w, double* gp,
-                          const double* tab, int rowbase, WinArgs a, GridDesc g, hipStream_t st);
+                          const double* tab, int rowbase, Aniso an, WinArgs a, GridDesc g,
+                          hipStream_t st);
 hipError_t launch_grad_sum(const double* gp, int nbuf, double* grad, long long n, hipStream_t st);
 
 hipError_t launch_to_f64(int prec, const void* src_plane, double* dst, long long n,
@@ -87,7 +99,7 @@ hipError_t launch_check(int prec, const void* u, int nplanes, GridDesc g, double
 
 hipError_t launch_grad_final(const double* grad, const double* tab, const double* sa,
                              const double* ss, double* dsa, double* dss, GridDesc g, double dt,
-                             hipStream_t st);
+                             bool aniso, hipStream_t st);
 
 hipError_t launch_fill_zero(void* p, long long bytes, hipStream_t st);
 

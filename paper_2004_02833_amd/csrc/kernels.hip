@@ -120,6 +120,20 @@ __device__ __forceinline__ void decay(double c, double tau, double& a, double& b
     b = (c == 0.0) ? tau : -expm1(-c * tau) / c;
 }
 
+// d beta / d c for beta = (1 - exp(-c tau))/c:  -tau^2 F(c tau) with
+// F(z) = (1 - (1+z) e^{-z}) / z^2 = sum_k (-1)^k (k+1) z^k / (k+2)!,
+// summed as a series for |z| < 1e-2 (truncation below 1e-16 relative).
+__device__ __forceinline__ double dbeta_series(double z, double tau) {
+    const double F = 0.5 + z * (-1.0 / 3.0 + z * (1.0 / 8.0 + z * (-1.0 / 30.0 + z * (1.0 / 144.0 - z / 840.0))));
+    return -tau * tau * F;
+}
+
+__device__ __forceinline__ double dbeta_dc(double c, double tau, double alpha, double beta) {
+    const double z = c * tau;
+    if (fabs(z) < 1e-2) return dbeta_series(z, tau);
+    return (tau * alpha - beta) / c;
+}
+
 // Cell k + b (b in {0,1}^3, sign +1) or k - b (sign -1), periodic.
 __device__ __forceinline__ long long shifted(long long c, int bx, int by, int bz, bool minus,
                                              const GridDesc& g) {
@@ -176,11 +190,51 @@ __global__ void k_tables(const double* __restrict__ sa, const double* __restrict
     }
 }
 
+// Anisotropic scattering: the coefficient of degree l is
+// c_l = sigma_a + (1 - g_l) sigma_s, so every grid keeps the means of
+// sigma_a and of sigma_s over the cells sharing its point (rows 2s, 2s + 1);
+// the sweeps form c_l and its decay factors per degree.  Row 18 holds q.
+__device__ __forceinline__ void means_at(const double* __restrict__ sa,
+                                         const double* __restrict__ ss, long long c, int s,
+                                         const GridDesc& g, double& ma, double& ms) {
+    const int bits = c_grid_bits[s];
+    const int ox = bits & 1, oy = (bits >> 1) & 1, oz = (bits >> 2) & 1;
+    double a = 0.0, b = 0.0;
+    int cnt = 0;
+    for (int bz = 0; bz <= oz; ++bz)
+        for (int by = 0; by <= oy; ++by)
+            for (int bx = 0; bx <= ox; ++bx) {
+                const long long k = shifted(c, bx, by, bz, false, g);
+                a += sa[k];
+                b += ss[k];
+                ++cnt;
+            }
+    ma = a / cnt;
+    ms = b / cnt;
+}
+
+__global__ void k_tables_aniso(const double* __restrict__ sa, const double* __restrict__ ss,
+                               const double* __restrict__ q, double* __restrict__ tab,
+                               GridDesc g) {
+    const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= g.ncell) return;
+    for (int s = 0; s < 8; ++s) {
+        double ma, ms;
+        means_at(sa, ss, c, s, g, ma, ms);
+        tab[(long long)(2 * s) * g.ncell + c] = ma;
+        tab[(long long)(2 * s + 1) * g.ncell + c] = ms;
+    }
+    tab[(long long)kTabQ * g.ncell + c] = q ? q[c] : 0.0;
+}
+
 hipError_t launch_tables(const double* sa, const double* ss, const double* q, double* tab,
-                         GridDesc g, double dt, hipStream_t st) {
+                         GridDesc g, double dt, bool aniso, hipStream_t st) {
     const int B = 256;
     const long long nb = (g.ncell + B - 1) / B;
-    hipLaunchKernelGGL(k_tables, dim3((unsigned)nb), dim3(B), 0, st, sa, ss, q, tab, g, dt);
+    if (aniso)
+        hipLaunchKernelGGL(k_tables_aniso, dim3((unsigned)nb), dim3(B), 0, st, sa, ss, q, tab, g);
+    else
+        hipLaunchKernelGGL(k_tables, dim3((unsigned)nb), dim3(B), 0, st, sa, ss, q, tab, g, dt);
     return hipGetLastError();
 }
 
@@ -340,17 +394,24 @@ __device__ __forceinline__ long long tile_cell(const TileMap& m, long long tile,
 //            backward one, so this is a forward-shaped stencil over w)
 enum SweepMode { kFwd = 0, kAdjTgt = 1, kAdjDual = 2 };
 
-template <class T, int K, int TPB, int CPL, int MODE>
+// ANI (anisotropic scattering): the table rows of the four target grids hold
+// the means of sigma_a and sigma_s; the decay factors of every (target
+// degree, grid) pair of the pass are formed once per cell from
+// c_l = mean sigma_a + (1 - g_l) mean sigma_s with the per-degree moments gl
+// and the substep length tau, and kept in LDS.
+template <class T, int K, int TPB, int CPL, int MODE, bool ANI>
 __global__ void __launch_bounds__(TPB) k_sweep_win(const T* __restrict__ us, T* __restrict__ u,
                                                    T* __restrict__ uw, double* __restrict__ gp,
                                                    const double* __restrict__ tab,
                                                    const int2* __restrict__ src,
                                                    const int2* __restrict__ tgt,
                                                    const typename Acc<T>::type* __restrict__ coef,
+                                                   const double* __restrict__ gl, double tau,
                                                    int rowbase, int N, int parity, int npass,
                                                    int per_xcd, long long ntile, TileMap tm,
                                                    GridDesc g) {
     static_assert(MODE == kFwd || CPL == 1, "transposed sweeps use one cell per lane");
+    static_assert(!(ANI && MODE == kAdjDual), "the dual side reads no decay factors");
     // the forward substep reads its sources from the state it updates
     const T* __restrict__ sv = MODE == kFwd ? u : us;
     using A = typename Acc<T>::type;
@@ -376,28 +437,51 @@ __global__ void __launch_bounds__(TPB) k_sweep_win(const T* __restrict__ us, T* 
         nb.zm = n0.off[5];
     }
     const long long ps = g.pstride;
-    // decay factors of the four target grids (rows 0..7), moment 0 (8, 9)
-    // and q (10) for the lane's cells, kept in LDS instead of registers
-    __shared__ double tl[11][TPB * CPL];
+    // decay factors for the lane's cells, kept in LDS instead of registers:
+    // isotropic: the four target grids (rows 0..7), moment 0 (8, 9), q (10);
+    // ANI: target degree t and grid f in rows 2 (4 t + f), 2 (4 t + f) + 1,
+    // q in row 8 K
+    constexpr int kRowQ = ANI ? 8 * K : 10;
+    __shared__ double tl[kRowQ + 1][TPB * CPL];
     const int tid = threadIdx.x;
-    if (MODE != kAdjDual) {
+    const int MU1 = N + 2;
+    const int L0 = parity + 2 * K * pass;
+    if (ANI) {
 #pragma unroll
-    for (int f = 0; f < 8; ++f)
+        for (int f = 0; f < 4; ++f)
 #pragma unroll
-        for (int k = 0; k < CPL; ++k)
-            tl[f][tid * CPL + k] = tab[(long long)(rowbase + f) * g.ncell + nb.c0 + k];
+            for (int k = 0; k < CPL; ++k) {
+                const double ma = tab[(long long)(rowbase + 2 * f) * g.ncell + nb.c0 + k];
+                const double ms = tab[(long long)(rowbase + 2 * f + 1) * g.ncell + nb.c0 + k];
+#pragma unroll
+                for (int t = 0; t < K; ++t) {
+                    if (L0 + 2 * t > N) continue;
+                    double a, b;
+                    decay(ma + (1.0 - gl[L0 + 2 * t]) * ms, tau, a, b);
+                    tl[2 * (4 * t + f)][tid * CPL + k] = a;
+                    tl[2 * (4 * t + f) + 1][tid * CPL + k] = b;
+                }
+            }
+    } else if (MODE != kAdjDual) {
+#pragma unroll
+        for (int f = 0; f < 8; ++f)
+#pragma unroll
+            for (int k = 0; k < CPL; ++k)
+                tl[f][tid * CPL + k] = tab[(long long)(rowbase + f) * g.ncell + nb.c0 + k];
     }
-    double ga[5] = {0, 0, 0, 0, 0}, gb[5] = {0, 0, 0, 0, 0};  // kAdjTgt gradient sums
+    // kAdjTgt gradient sums: per coefficient set (isotropic), or per grid
+    // with respect to the means of sigma_a (ga) and sigma_s (gb) (ANI)
+    double ga[5] = {0, 0, 0, 0, 0}, gb[5] = {0, 0, 0, 0, 0};
     if (MODE != kAdjDual && parity == 0) {
 #pragma unroll
         for (int k = 0; k < CPL; ++k) {
-            tl[8][tid * CPL + k] = tab[(long long)kTabMom0 * g.ncell + nb.c0 + k];
-            tl[9][tid * CPL + k] = tab[(long long)(kTabMom0 + 1) * g.ncell + nb.c0 + k];
-            tl[10][tid * CPL + k] = tab[(long long)kTabQ * g.ncell + nb.c0 + k];
+            if (!ANI) {
+                tl[8][tid * CPL + k] = tab[(long long)kTabMom0 * g.ncell + nb.c0 + k];
+                tl[9][tid * CPL + k] = tab[(long long)(kTabMom0 + 1) * g.ncell + nb.c0 + k];
+            }
+            tl[kRowQ][tid * CPL + k] = tab[(long long)kTabQ * g.ncell + nb.c0 + k];
         }
     }
-    const int MU1 = N + 2;
-    const int L0 = parity + 2 * K * pass;
     const int mumax = min(N, L0 + 2 * (K - 1));  // largest target |m| in the pass
     const int2* sd = src + (long long)pass * MU1 * (K + 1) * 2;
     const int2* td = tgt + (long long)pass * MU1 * K * 2;
@@ -502,7 +586,9 @@ __global__ void __launch_bounds__(TPB) k_sweep_win(const T* __restrict__ us, T* 
                 for (int ty = 0; ty < 2; ++ty) {
                     const int2 d = tdc[t * 2 + ty];
                     if (d.x < 0) continue;
-                    const int ra = d.y == kTabMom0 ? 8 : 2 * ((d.y >> 1) & 3);
+                    // moment 0 (row code kTabMom0) is grid G111, degree 0, under ANI
+                    const int ra = ANI ? 2 * (4 * t + ((d.y >> 1) & 3))
+                                       : d.y == kTabMom0 ? 8 : 2 * ((d.y >> 1) & 3);
                     T* ut = u + (long long)d.x * ps + nb.c0;
                     A old[CPL];
                     if constexpr (MODE == kFwd)
@@ -513,7 +599,7 @@ __global__ void __launch_bounds__(TPB) k_sweep_win(const T* __restrict__ us, T* 
                     if constexpr (MODE == kFwd) {
 #pragma unroll
                         for (int k = 0; k < CPL; ++k) {
-                            const double q = d.y == kTabMom0 ? tl[10][tid * CPL + k] : 0.0;
+                            const double q = d.y == kTabMom0 ? tl[kRowQ][tid * CPL + k] : 0.0;
                             nv[k] = tl[ra][tid * CPL + k] * (double)old[k] +
                                     tl[ra + 1][tid * CPL + k] * (q - (double)S[0][t][ty][k]);
                         }
@@ -523,15 +609,36 @@ __global__ void __launch_bounds__(TPB) k_sweep_win(const T* __restrict__ us, T* 
                         // old[0] is lam_i; the old u_i comes from the source state
                         const double lam = (double)old[0];
                         const double uo = (double)ld(sv + (long long)d.x * ps + nb.c0);
-                        const double q = d.y == kTabMom0 ? tl[10][tid] : 0.0;
+                        const double q = d.y == kTabMom0 ? tl[kRowQ][tid] : 0.0;
                         const double r = q - (double)S[0][t][ty][0];
-                        const int set = d.y == kTabMom0 ? 4 : ((d.y >> 1) & 3);
+                        if constexpr (ANI) {
+                            // dL/dc = lam (u d alpha/dc + r d beta/dc), with c
+                            // recovered from the factors: c = (1 - alpha)/beta
+                            const double al = tl[ra][tid], be = tl[ra + 1][tid];
+                            const double om = 1.0 - al;
+                            double db;
+                            if (om < 1e-2)
+                                db = dbeta_series(tau * om / be, tau);
+                            else
+                                db = (tau * al - be) * be / om;
+                            const double gx = lam * (uo * (-tau * al) + r * db);
+                            const double ws = 1.0 - gl[L0 + 2 * t];
+                            const int f = (d.y >> 1) & 3;
 #pragma unroll
-                        for (int s5 = 0; s5 < 5; ++s5)
-                            if (s5 == set) {
-                                ga[s5] += lam * uo;
-                                gb[s5] += lam * r;
-                            }
+                            for (int f4 = 0; f4 < 4; ++f4)
+                                if (f4 == f) {
+                                    ga[f4] += gx;
+                                    gb[f4] += ws * gx;
+                                }
+                        } else {
+                            const int set = d.y == kTabMom0 ? 4 : ((d.y >> 1) & 3);
+#pragma unroll
+                            for (int s5 = 0; s5 < 5; ++s5)
+                                if (s5 == set) {
+                                    ga[s5] += lam * uo;
+                                    gb[s5] += lam * r;
+                                }
+                        }
                         const double wv[1] = {tl[ra + 1][tid] * lam};
                         if (live) st(uw + (long long)d.x * ps + nb.c0, wv[0]);
                         nv[0] = tl[ra][tid] * lam;
@@ -560,7 +667,7 @@ __global__ void __launch_bounds__(TPB) k_sweep_win(const T* __restrict__ us, T* 
             const int gbase = parity ? 4 : 0;
 #pragma unroll
             for (int s5 = 0; s5 < 5; ++s5) {
-                if (s5 == 4 && parity != 0) continue;
+                if (s5 == 4 && (parity != 0 || ANI)) continue;
                 const int row = s5 == 4 ? kTabMom0 : 2 * (gbase + s5);
                 gq[(long long)row * g.ncell] += ga[s5];
                 gq[(long long)(row + 1) * g.ncell] += gb[s5];
@@ -587,9 +694,9 @@ int win_depth(int prec) { return prec == kF64 ? PM_WIN_K64 : PM_WIN_K32; }
 #define PM_CPL16 2
 #endif
 
-template <class T, int K, int CPL, int MODE>
+template <class T, int K, int CPL, int MODE, bool ANI>
 static void launch_win_t(const T* us, T* u, T* uw, double* gp, const double* tab, int rowbase,
-                         WinArgs a, GridDesc g, hipStream_t st) {
+                         Aniso an, WinArgs a, GridDesc g, hipStream_t st) {
     using A = typename Acc<T>::type;
     constexpr int TPB = 256 / CPL;
     TileMap tm{0, 1, 1, 1};
@@ -606,54 +713,68 @@ static void launch_win_t(const T* us, T* u, T* uw, double* gp, const double* tab
     }
     const int per_xcd = (int)((ntile + kXcds - 1) / kXcds);
     const unsigned nwg = (unsigned)((long long)kXcds * per_xcd * a.npass);
-    hipLaunchKernelGGL((k_sweep_win<T, K, TPB, CPL, MODE>), dim3(nwg), dim3(TPB), 0, st, us, u,
-                       uw, gp, tab, a.src, a.tgt, (const A*)a.coef, rowbase, a.N, a.parity,
-                       a.npass, per_xcd, ntile, tm, g);
+    hipLaunchKernelGGL((k_sweep_win<T, K, TPB, CPL, MODE, ANI>), dim3(nwg), dim3(TPB), 0, st, us,
+                       u, uw, gp, tab, a.src, a.tgt, (const A*)a.coef, an.gl, an.tau, rowbase, a.N,
+                       a.parity, a.npass, per_xcd, ntile, tm, g);
 }
 
-hipError_t launch_sweep_win(int prec, void* u, const double* tab, int rowbase, WinArgs a,
-                            GridDesc g, hipStream_t st) {
+template <class T, int K, int CPL>
+static void launch_fwd(void* u, const double* tab, int rowbase, Aniso an, WinArgs a, GridDesc g,
+                       hipStream_t st) {
+    if (an.gl)
+        launch_win_t<T, K, CPL, kFwd, true>((const T*)u, (T*)u, nullptr, nullptr, tab, rowbase, an,
+                                            a, g, st);
+    else
+        launch_win_t<T, K, CPL, kFwd, false>((const T*)u, (T*)u, nullptr, nullptr, tab, rowbase,
+                                             an, a, g, st);
+}
+
+hipError_t launch_sweep_win(int prec, void* u, const double* tab, int rowbase, Aniso an,
+                            WinArgs a, GridDesc g, hipStream_t st) {
     if (a.K != win_depth(prec)) return hipErrorInvalidValue;
     // several cells per lane need whole lane groups within every row
-#define PM_FWD(T, K, C) launch_win_t<T, K, C, kFwd>((const T*)u, (T*)u, nullptr, nullptr, tab, rowbase, a, g, st)
     if (prec == kF64) {
         if (PM_CPL64 > 1 && g.nx % PM_CPL64 == 0)
-            PM_FWD(double, PM_WIN_K64, PM_CPL64);
+            launch_fwd<double, PM_WIN_K64, PM_CPL64>(u, tab, rowbase, an, a, g, st);
         else
-            PM_FWD(double, PM_WIN_K64, 1);
+            launch_fwd<double, PM_WIN_K64, 1>(u, tab, rowbase, an, a, g, st);
     } else if (prec == kF32) {
         if (PM_CPL32 > 1 && g.nx % PM_CPL32 == 0)
-            PM_FWD(float, PM_WIN_K32, PM_CPL32);
+            launch_fwd<float, PM_WIN_K32, PM_CPL32>(u, tab, rowbase, an, a, g, st);
         else
-            PM_FWD(float, PM_WIN_K32, 1);
+            launch_fwd<float, PM_WIN_K32, 1>(u, tab, rowbase, an, a, g, st);
     } else {
         if (PM_CPL16 > 1 && g.nx % PM_CPL16 == 0)
-            PM_FWD(bf16s, PM_WIN_K32, PM_CPL16);
+            launch_fwd<bf16s, PM_WIN_K32, PM_CPL16>(u, tab, rowbase, an, a, g, st);
         else
-            PM_FWD(bf16s, PM_WIN_K32, 1);
+            launch_fwd<bf16s, PM_WIN_K32, 1>(u, tab, rowbase, an, a, g, st);
     }
-#undef PM_FWD
     return hipGetLastError();
 }
 
+template <class T, int K>
+static void launch_adj_t(int side, const void* us, void* lam, void* w, double* gp,
+                         const double* tab, int rowbase, Aniso an, WinArgs a, GridDesc g,
+                         hipStream_t st) {
+    if (side == 1)
+        launch_win_t<T, K, 1, kAdjDual, false>((const T*)us, (T*)lam, nullptr, nullptr, tab, 0, an,
+                                               a, g, st);
+    else if (an.gl)
+        launch_win_t<T, K, 1, kAdjTgt, true>((const T*)us, (T*)lam, (T*)w, gp, tab, rowbase, an, a,
+                                             g, st);
+    else
+        launch_win_t<T, K, 1, kAdjTgt, false>((const T*)us, (T*)lam, (T*)w, gp, tab, rowbase, an,
+                                              a, g, st);
+}
+
 hipError_t launch_adj_win(int prec, int side, const void* us, void* lam, void* w, double* gp,
-                          const double* tab, int rowbase, WinArgs a, GridDesc g, hipStream_t st) {
+                          const double* tab, int rowbase, Aniso an, WinArgs a, GridDesc g,
+                          hipStream_t st) {
     if (a.K != win_depth(prec) || prec == kBF16) return hipErrorInvalidValue;
-    if (prec == kF64) {
-        if (side == 0)
-            launch_win_t<double, PM_WIN_K64, 1, kAdjTgt>((const double*)us, (double*)lam, (double*)w,
-                                                         gp, tab, rowbase, a, g, st);
-        else
-            launch_win_t<double, PM_WIN_K64, 1, kAdjDual>((const double*)us, (double*)lam, nullptr,
-                                                          nullptr, tab, rowbase, a, g, st);
-    } else {
-        if (side == 0)
-            launch_win_t<float, PM_WIN_K32, 1, kAdjTgt>((const float*)us, (float*)lam, (float*)w,
-                                                       gp, tab, rowbase, a, g, st);
-        else
-            launch_win_t<float, PM_WIN_K32, 1, kAdjDual>((const float*)us, (float*)lam, nullptr,
-                                                        nullptr, tab, rowbase, a, g, st);
-    }
+    if (prec == kF64)
+        launch_adj_t<double, PM_WIN_K64>(side, us, lam, w, gp, tab, rowbase, an, a, g, st);
+    else
+        launch_adj_t<float, PM_WIN_K32>(side, us, lam, w, gp, tab, rowbase, an, a, g, st);
     return hipGetLastError();
 }
 
@@ -833,17 +954,6 @@ hipError_t launch_check(int prec, const void* u, int nplanes, GridDesc g, double
 // above); what remains is the chain rule from the decay factors to the
 // cell-centred medium.
 
-// d beta / d c for beta = (1 - exp(-c tau))/c:  -tau^2 F(c tau) with
-// F(z) = (1 - (1+z) e^{-z}) / z^2 = sum_k (-1)^k (k+1) z^k / (k+2)!,
-// summed as a series for |z| < 1e-2 (truncation below 1e-16 relative).
-__device__ __forceinline__ double dbeta_dc(double c, double tau, double alpha, double beta) {
-    const double z = c * tau;
-    if (fabs(z) < 1e-2) {
-        const double F = 0.5 + z * (-1.0 / 3.0 + z * (1.0 / 8.0 + z * (-1.0 / 30.0 + z * (1.0 / 144.0 - z / 840.0))));
-        return -tau * tau * F;
-    }
-    return (tau * alpha - beta) / c;
-}
 
 // Chain rule to the cell-centred medium: per set s the coefficient c_s on
 // the set's points is the mean of (sigma_a [+ sigma_s]) over 2^k cells
@@ -882,11 +992,43 @@ __global__ void k_grad_final(const double* __restrict__ grad, const double* __re
     if (dss) dss[c] = ts;
 }
 
+// Anisotropic scattering: the sweeps already accumulated dL/d(mean sigma_a)
+// and dL/d(mean sigma_s) per grid (rows 2s, 2s + 1); only the transpose of
+// the means remains.
+__global__ void k_grad_final_aniso(const double* __restrict__ grad, double* __restrict__ dsa,
+                                   double* __restrict__ dss, GridDesc g) {
+    const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= g.ncell) return;
+    double ta = 0.0, ts = 0.0;
+    for (int s = 0; s < 8; ++s) {
+        const int bits = c_grid_bits[s];
+        const int ox = bits & 1, oy = (bits >> 1) & 1, oz = (bits >> 2) & 1;
+        double aa = 0.0, as = 0.0;
+        int cnt = 0;
+        for (int bz = 0; bz <= oz; ++bz)
+            for (int by = 0; by <= oy; ++by)
+                for (int bx = 0; bx <= ox; ++bx) {
+                    const long long k = shifted(c, bx, by, bz, true, g);
+                    aa += grad[(long long)(2 * s) * g.ncell + k];
+                    as += grad[(long long)(2 * s + 1) * g.ncell + k];
+                    ++cnt;
+                }
+        ta += aa / cnt;
+        ts += as / cnt;
+    }
+    if (dsa) dsa[c] = ta;
+    if (dss) dss[c] = ts;
+}
+
 hipError_t launch_grad_final(const double* grad, const double* tab, const double* sa,
                              const double* ss, double* dsa, double* dss, GridDesc g, double dt,
-                             hipStream_t st) {
+                             bool aniso, hipStream_t st) {
     const unsigned nb = (unsigned)((g.ncell + 255) / 256);
-    hipLaunchKernelGGL(k_grad_final, dim3(nb), dim3(256), 0, st, grad, tab, sa, ss, dsa, dss, g, dt);
+    if (aniso)
+        hipLaunchKernelGGL(k_grad_final_aniso, dim3(nb), dim3(256), 0, st, grad, dsa, dss, g);
+    else
+        hipLaunchKernelGGL(k_grad_final, dim3(nb), dim3(256), 0, st, grad, tab, sa, ss, dsa, dss,
+                           g, dt);
     return hipGetLastError();
 }
 

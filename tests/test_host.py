@@ -95,6 +95,14 @@ def test_validation_before_device():
             pm.pm_set_merge(bad)
         assert e.value.code == pm.PM_EINVAL
     pm.pm_set_merge(1)
+    for bad in ([np.nan], [0.5, 1.5], [-1.2], [0.0] * 64):
+        with pytest.raises(pm.PmError) as e:
+            pm.pm_set_scattering(bad)
+        assert e.value.code == pm.PM_EINVAL
+    assert pm.lib().pm_set_scattering(None, 2) == pm.PM_EINVAL
+    assert pm.lib().pm_set_scattering(None, -1) == pm.PM_EINVAL
+    pm.pm_set_scattering([1.0, -1.0, 0.25])
+    pm.pm_set_scattering(None)
     for bad in (-1, 64):
         with pytest.raises(pm.PmError):
             pm.pm_flux_nnz(bad)

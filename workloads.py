@@ -173,6 +173,15 @@ def p39_smooth(seed=2, n=64, N=39, nsteps=100, name="p39_smooth"):
                     extra={"centres": centres.tolist()})
 
 
+def p39_aniso(seed=2, n=64, N=39, nsteps=100, asym=0.8):
+    """The p39_smooth recipe with anisotropic (forward-peaked) scattering:
+    Henyey-Greenstein phase function of asymmetry 0.8, whose Legendre
+    moments are g_l = 0.8^l, so degree l has c_l = sigma_a + (1 - g_l) sigma_s."""
+    w = p39_smooth(seed=seed, n=n, N=N, nsteps=nsteps, name="p39_aniso")
+    w.extra["scattering"] = [asym ** l for l in range(1, N + 1)]
+    return w
+
+
 def p39_large(seed=2, n=160, N=39, nsteps=50):
     """The p39_smooth recipe at 160^3.  Drawing 6.5e9 normals on the host
     takes about a minute, so the N(0, 1e-3^2) noise of moments i >= 1 is
@@ -250,6 +259,7 @@ RECIPES = {
     "p7_lattice": p7_lattice,
     "p39_smooth": p39_smooth,
     "p39_large": p39_large,
+    "p39_aniso": p39_aniso,
     "p7_adjoint": p7_adjoint,
     "reactor": reactor,
 }
