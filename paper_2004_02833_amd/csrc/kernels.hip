@@ -13,13 +13,18 @@
 
 #include "kernels.h"
 
-// Target degrees per pass (registers vs re-reading the shared source degree):
-// K = 3 measured best for FP64 and FP32 with the decay factors kept in LDS.
+// Target degrees per pass: registers (hence resident waves) against
+// re-reading the source degree that adjacent passes share.  Measured on
+// P39 64^3: FP64 K = 3 (148 VGPRs, 3 waves/SIMD; K = 2 equal), FP32 K = 2
+// (70 VGPRs, 7 waves/SIMD: 312 vs 298 GDoF/s at K = 3), BF16 K = 3.
 #ifndef PM_WIN_K64
 #define PM_WIN_K64 3
 #endif
 #ifndef PM_WIN_K32
-#define PM_WIN_K32 3
+#define PM_WIN_K32 2
+#endif
+#ifndef PM_WIN_K16
+#define PM_WIN_K16 3
 #endif
 
 namespace pm {
@@ -676,7 +681,7 @@ __global__ void __launch_bounds__(TPB) k_sweep_win(const T* __restrict__ us, T* 
     }
 }
 
-int win_depth(int prec) { return prec == kF64 ? PM_WIN_K64 : PM_WIN_K32; }
+int win_depth(int prec) { return prec == kF64 ? PM_WIN_K64 : prec == kF32 ? PM_WIN_K32 : PM_WIN_K16; }
 
 
 // Launch shape, measured on P39 64^3.  Cells per lane: 1 for FP64 and FP32
@@ -745,9 +750,9 @@ hipError_t launch_sweep_win(int prec, void* u, const double* tab, int rowbase, A
             launch_fwd<float, PM_WIN_K32, 1>(u, tab, rowbase, an, a, g, st);
     } else {
         if (PM_CPL16 > 1 && g.nx % PM_CPL16 == 0)
-            launch_fwd<bf16s, PM_WIN_K32, PM_CPL16>(u, tab, rowbase, an, a, g, st);
+            launch_fwd<bf16s, PM_WIN_K16, PM_CPL16>(u, tab, rowbase, an, a, g, st);
         else
-            launch_fwd<bf16s, PM_WIN_K32, 1>(u, tab, rowbase, an, a, g, st);
+            launch_fwd<bf16s, PM_WIN_K16, 1>(u, tab, rowbase, an, a, g, st);
     }
     return hipGetLastError();
 }
