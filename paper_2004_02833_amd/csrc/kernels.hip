@@ -477,7 +477,8 @@ __global__ void __launch_bounds__(TPB) k_sweep_win(const T* __restrict__ us, T* 
     // kAdjTgt gradient sums: per coefficient set (isotropic), or per grid
     // with respect to the means of sigma_a (ga) and sigma_s (gb) (ANI)
     double ga[5] = {0, 0, 0, 0, 0}, gb[5] = {0, 0, 0, 0, 0};
-    if (MODE != kAdjDual && parity == 0) {
+    // moment 0 (and its source q) is a target of the first even pass only
+    if (MODE != kAdjDual && parity == 0 && pass == 0) {
 #pragma unroll
         for (int k = 0; k < CPL; ++k) {
             if (!ANI) {
