@@ -15,10 +15,11 @@
 
 // Target degrees per pass: registers (hence resident waves) against
 // re-reading the source degree that adjacent passes share.  Measured on
-// P39 64^3: FP64 K = 3 (148 VGPRs, 3 waves/SIMD; K = 2 equal), FP32 K = 2
-// (70 VGPRs, 7 waves/SIMD: 312 vs 298 GDoF/s at K = 3), BF16 K = 3.
+// P39 64^3: FP64 K = 2 (96 VGPRs with whole-row waves, 5 waves/SIMD: 173 vs
+// 163 GDoF/s at K = 3), FP32 K = 2 (70 VGPRs, 7 waves/SIMD: 312 vs 298),
+// BF16 K = 3.
 #ifndef PM_WIN_K64
-#define PM_WIN_K64 3
+#define PM_WIN_K64 2
 #endif
 #ifndef PM_WIN_K32
 #define PM_WIN_K32 2
@@ -327,7 +328,31 @@ struct LaneNbr {
     int yp, ym, zp, zm; // row offsets of the y / z neighbours: forward, backward
 };
 
-template <class T, int CPL>
+// Wavefront rotations by one lane (DPP wave_rol:1 / wave_ror:1): lane i
+// receives the value of lane i + 1 (next) or i - 1 (prev), modulo 64.
+// Every lane of the wave must be active.
+__device__ __forceinline__ uint32_t rot_next(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x134, 0xf, 0xf, false);
+}
+__device__ __forceinline__ uint32_t rot_prev(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x13C, 0xf, 0xf, false);
+}
+template <bool NEXT> __device__ __forceinline__ double rot(double v) {
+    const uint32_t lo = (uint32_t)__double2loint(v), hi = (uint32_t)__double2hiint(v);
+    return __hiloint2double((int)(NEXT ? rot_next(hi) : rot_prev(hi)),
+                            (int)(NEXT ? rot_next(lo) : rot_prev(lo)));
+}
+template <bool NEXT> __device__ __forceinline__ float rot(float v) {
+    return __uint_as_float(NEXT ? rot_next(__float_as_uint(v)) : rot_prev(__float_as_uint(v)));
+}
+template <bool NEXT> __device__ __forceinline__ uint16_t rot(uint16_t v) {
+    return (uint16_t)(NEXT ? rot_next(v) : rot_prev(v));
+}
+
+// XROT: every wave holds one whole row (64 lanes x CPL cells = nx), so the
+// x neighbour outside a lane's cells, periodic wrap included, is held by the
+// next or previous lane and comes by a rotation instead of a load.
+template <class T, int CPL, bool XROT>
 __device__ __forceinline__ void win_fetch(Raw<T, CPL>& r, const T* __restrict__ u, int2 d,
                                           const LaneNbr& nb, long long ps) {
     using V = typename Pack<T, CPL>::V;
@@ -337,7 +362,7 @@ __device__ __forceinline__ void win_fetch(Raw<T, CPL>& r, const T* __restrict__ 
         r.c = *(const V*)p;
         r.y = *(const V*)(p + ((d.y & 2) ? nb.ym : nb.yp));
         r.z = *(const V*)(p + ((d.y & 4) ? nb.zm : nb.zp));
-        r.xe = *(const S1*)(p + ((d.y & 1) ? nb.xem : nb.xep));
+        if (!XROT) r.xe = *(const S1*)(p + ((d.y & 1) ? nb.xem : nb.xep));
     } else {
         r.c = V{};
         r.y = V{};
@@ -404,7 +429,7 @@ enum SweepMode { kFwd = 0, kAdjTgt = 1, kAdjDual = 2 };
 // degree, grid) pair of the pass are formed once per cell from
 // c_l = mean sigma_a + (1 - g_l) mean sigma_s with the per-degree moments gl
 // and the substep length tau, and kept in LDS.
-template <class T, int K, int TPB, int CPL, int MODE, bool ANI>
+template <class T, int K, int TPB, int CPL, int MODE, bool ANI, bool XROT>
 __global__ void __launch_bounds__(TPB) k_sweep_win(const T* __restrict__ us, T* __restrict__ u,
                                                    T* __restrict__ uw, double* __restrict__ gp,
                                                    const double* __restrict__ tab,
@@ -417,6 +442,7 @@ __global__ void __launch_bounds__(TPB) k_sweep_win(const T* __restrict__ us, T* 
                                                    GridDesc g) {
     static_assert(MODE == kFwd || CPL == 1, "transposed sweeps use one cell per lane");
     static_assert(!(ANI && MODE == kAdjDual), "the dual side reads no decay factors");
+    static_assert(!XROT || MODE == kFwd, "row rotation only in the forward sweep");
     // the forward substep reads its sources from the state it updates
     const T* __restrict__ sv = MODE == kFwd ? u : us;
     using A = typename Acc<T>::type;
@@ -510,7 +536,7 @@ __global__ void __launch_bounds__(TPB) k_sweep_win(const T* __restrict__ us, T* 
 #pragma unroll
     for (int b = 0; b <= K; ++b)
 #pragma unroll
-        for (int ty = 0; ty < 2; ++ty) win_fetch<T, CPL>(R[b][ty], sv, sd[b * 2 + ty], nb, ps);
+        for (int ty = 0; ty < 2; ++ty) win_fetch<T, CPL, XROT>(R[b][ty], sv, sd[b * 2 + ty], nb, ps);
 #pragma unroll
     for (int w = 0; w < 3; ++w)
 #pragma unroll
@@ -534,9 +560,27 @@ __global__ void __launch_bounds__(TPB) k_sweep_win(const T* __restrict__ us, T* 
                 unpack<T, CPL, A>(R[b][ty].c, vc);
                 unpack<T, CPL, A>(R[b][ty].y, vy);
                 unpack<T, CPL, A>(R[b][ty].z, vz);
-                const A xv = (A)s1_val<T>(R[b][ty].xe);
-                A dx[CPL], dy[CPL], dz[CPL];
                 const bool back = e.y & 1;
+                A xv;
+                if constexpr (XROT) {
+                    // first cell of the next lane, or last cell of the previous one
+                    using S1 = typename Pack<T, CPL>::S1;
+                    S1 first, last;
+                    if constexpr (CPL == 1) {
+                        first = last = (S1)R[b][ty].c;
+                    } else if constexpr (std::is_same<T, bf16s>::value) {
+                        static_assert(CPL == 2, "bf16 rows by rotation: two cells per lane");
+                        first = (S1)(R[b][ty].c & 0xffffu);
+                        last = (S1)(R[b][ty].c >> 16);
+                    } else {
+                        first = R[b][ty].c[0];
+                        last = R[b][ty].c[CPL - 1];
+                    }
+                    xv = (A)s1_val<T>(back ? rot<false>(last) : rot<true>(first));
+                } else {
+                    xv = (A)s1_val<T>(R[b][ty].xe);
+                }
+                A dx[CPL], dy[CPL], dz[CPL];
 #pragma unroll
                 for (int k = 0; k < CPL; ++k) {
                     const A xn = back ? (k > 0 ? vc[k > 0 ? k - 1 : 0] : xv)
@@ -545,7 +589,7 @@ __global__ void __launch_bounds__(TPB) k_sweep_win(const T* __restrict__ us, T* 
                     dy[k] = vy[k] - vc[k];
                     dz[k] = vz[k] - vc[k];
                 }
-                if (mu <= mumax) win_fetch<T, CPL>(R[b][ty], sv, sdn[b * 2 + ty], nb, ps);
+                if (mu <= mumax) win_fetch<T, CPL, XROT>(R[b][ty], sv, sdn[b * 2 + ty], nb, ps);
                 if (e.x < 0) continue;
 #pragma unroll
                 for (int side = 0; side < 2; ++side) {
@@ -719,9 +763,15 @@ static void launch_win_t(const T* us, T* u, T* uw, double* gp, const double* tab
     }
     const int per_xcd = (int)((ntile + kXcds - 1) / kXcds);
     const unsigned nwg = (unsigned)((long long)kXcds * per_xcd * a.npass);
-    hipLaunchKernelGGL((k_sweep_win<T, K, TPB, CPL, MODE, ANI>), dim3(nwg), dim3(TPB), 0, st, us,
-                       u, uw, gp, tab, a.src, a.tgt, (const A*)a.coef, an.gl, an.tau, rowbase, a.N,
-                       a.parity, a.npass, per_xcd, ntile, tm, g);
+    // one whole row per wave: x neighbours by lane rotation
+    if (MODE == kFwd && sw == g.nx && g.nx == 64 * CPL)
+        hipLaunchKernelGGL((k_sweep_win<T, K, TPB, CPL, MODE, ANI, MODE == kFwd>), dim3(nwg),
+                           dim3(TPB), 0, st, us, u, uw, gp, tab, a.src, a.tgt, (const A*)a.coef,
+                           an.gl, an.tau, rowbase, a.N, a.parity, a.npass, per_xcd, ntile, tm, g);
+    else
+        hipLaunchKernelGGL((k_sweep_win<T, K, TPB, CPL, MODE, ANI, false>), dim3(nwg), dim3(TPB),
+                           0, st, us, u, uw, gp, tab, a.src, a.tgt, (const A*)a.coef, an.gl,
+                           an.tau, rowbase, a.N, a.parity, a.npass, per_xcd, ntile, tm, g);
 }
 
 template <class T, int K, int CPL>
