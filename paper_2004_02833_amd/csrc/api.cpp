@@ -60,7 +60,9 @@ struct Ctx {
     bool aniso = false;     // some g_l != 0 for 1 <= l <= N
     double* gl = nullptr;   // g_0 .. g_N on the device (anisotropic scattering)
     void* win_mem = nullptr;  // window sweep streams (both parities)
-    pm::WinArgs win[2]{};
+    void* adj_mem = nullptr;  // streams of the transposed sweeps when their depth differs
+    pm::WinArgs win[2]{};     // forward sweeps
+    pm::WinArgs wadj[2]{};    // transposed sweeps (pm_grad)
     double* plane64 = nullptr;
     double* red = nullptr;
     unsigned long long* redc = nullptr;
@@ -127,6 +129,7 @@ void release() {
     dfree(C.sig);
     dfree(C.gl);
     dfree(C.win_mem);
+    dfree(C.adj_mem);
     dfree(C.plane64);
     dfree(C.red);
     dfree(C.redc);
@@ -154,10 +157,9 @@ long long plane_stride(long long ncell) {
 // Streams of the window sweep (layout documented in kernels.h).  Every
 // nonzero flux entry with a target of the sweep's parity must land in exactly
 // one coefficient slot; the count is checked.
-int build_window_tables() {
+int build_window_tables(int K, pm::WinArgs (&win)[2], void** mem) {
     const pm::Layout& L = C.L;
     const int N = C.N, V = C.V, MU1 = N + 2;
-    const int K = pm::win_depth(C.prec);
     std::unordered_map<long long, double> flux;
     long long nnz_par[2] = {0, 0};
     for (const pm::FluxEntry& e : pm::flux_entries(N)) {
@@ -176,10 +178,10 @@ int build_window_tables() {
     } H[2];
     for (int p = 0; p < 2; ++p) {
         const int npass = N >= p ? (N - p) / (2 * K) + 1 : 0;
-        C.win[p].N = N;
-        C.win[p].parity = p;
-        C.win[p].K = K;
-        C.win[p].npass = npass;
+        win[p].N = N;
+        win[p].parity = p;
+        win[p].K = K;
+        win[p].npass = npass;
         Host& h = H[p];
         h.src.assign((size_t)npass * MU1 * (K + 1) * 2, make_int2(-1, 0));
         h.tgt.assign((size_t)npass * MU1 * K * 2, make_int2(-1, 0));
@@ -238,9 +240,9 @@ int build_window_tables() {
         off[p][1] = total; total += up(H[p].tgt.size() * sizeof(int2));
         off[p][2] = total; total += up(H[p].coef.size() * es);
     }
-    int rc = dmalloc(&C.win_mem, total, "window streams");
+    int rc = dmalloc(mem, total, "window streams");
     if (rc) return rc;
-    char* base = (char*)C.win_mem;
+    char* base = (char*)*mem;
     for (int p = 0; p < 2; ++p) {
         if (!H[p].src.empty())
             HIPCHK(hipMemcpy(base + off[p][0], H[p].src.data(), H[p].src.size() * sizeof(int2), hipMemcpyHostToDevice));
@@ -254,9 +256,9 @@ int build_window_tables() {
                 HIPCHK(hipMemcpy(base + off[p][2], c32.data(), c32.size() * es, hipMemcpyHostToDevice));
             }
         }
-        C.win[p].src = (const int2*)(base + off[p][0]);
-        C.win[p].tgt = (const int2*)(base + off[p][1]);
-        C.win[p].coef = base + off[p][2];
+        win[p].src = (const int2*)(base + off[p][0]);
+        win[p].tgt = (const int2*)(base + off[p][1]);
+        win[p].coef = base + off[p][2];
     }
     return PM_OK;
 }
@@ -431,7 +433,13 @@ int pm_init_cells(int N, int nx, int ny, int nz, double dx, double dy, double dz
     TRY(dmalloc(&C.plane64, sizeof(double) * (size_t)ncell, "plane"));
     TRY(dmalloc(&C.red, sizeof(double) * (C.npart + 1), "reduction"));
     TRY(dmalloc(&C.redc, sizeof(unsigned long long) * (C.npart + 1), "reduction"));
-    TRY(build_window_tables());
+    TRY(build_window_tables(pm::win_depth(C.prec), C.win, &C.win_mem));
+    if (C.prec != PM_BF16 && pm::adj_depth(C.prec) != pm::win_depth(C.prec)) {
+        TRY(build_window_tables(pm::adj_depth(C.prec), C.wadj, &C.adj_mem));
+    } else {
+        C.wadj[0] = C.win[0];
+        C.wadj[1] = C.win[1];
+    }
     hipStream_t s = C.stream();
     auto dev = [&](hipError_t err, const char* what) -> int {
         if (err == hipSuccess) return PM_OK;
@@ -584,7 +592,7 @@ int pm_grad(const double* dL_du0, double* dsa, double* dss) {
         }                                                                              \
     } while (0)
     const int segs = T > 0 ? ck : 1;
-    const int np0 = C.win[0].npass, np1 = C.win[1].npass;
+    const int np0 = C.wadj[0].npass, np1 = C.wadj[1].npass;
     const size_t gpb = sizeof(double) * pm::kGradRows * (size_t)n;  // one pass of gradient rows
     {
         size_t fr = 0, tot = 0;
@@ -632,12 +640,12 @@ int pm_grad(const double* dL_du0, double* dsa, double* dss) {
             for (int j = 0; j < 3; ++j) {
                 const int p = pars[j];
                 const pm::Aniso an{C.aniso ? C.gl : nullptr, p ? 0.5 * C.dt : C.dt};
-                if (C.win[p].npass > 0)
+                if (C.wadj[p].npass > 0)
                     HIPG(pm::launch_adj_win(C.prec, 0, olds[j], lam, w, gp_par[p], C.tab,
-                                            p ? 8 : 0, an, C.win[p], C.g, s));
-                if (C.win[1 - p].npass > 0)
+                                            p ? 8 : 0, an, C.wadj[p], C.g, s));
+                if (C.wadj[1 - p].npass > 0)
                     HIPG(pm::launch_adj_win(C.prec, 1, w, lam, nullptr, nullptr, C.tab, 0, an,
-                                            C.win[1 - p], C.g, s));
+                                            C.wadj[1 - p], C.g, s));
             }
         }
     }

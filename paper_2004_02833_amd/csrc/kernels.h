@@ -52,8 +52,10 @@ struct WinArgs {
     const void* coef;  // values of the accumulation type
 };
 
-// Target degrees per pass used for a storage precision.
+// Target degrees per pass of the forward sweeps and of the transposed ones
+// (pm_grad) for a storage precision.
 int win_depth(int prec);
+int adj_depth(int prec);
 
 // Anisotropic scattering: gl = device array of g_0 .. g_N (g_0 = 1), or
 // nullptr for the isotropic tables; tau = length of the substep.

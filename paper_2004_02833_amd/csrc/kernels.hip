@@ -15,11 +15,15 @@
 
 // Target degrees per pass: registers (hence resident waves) against
 // re-reading the source degree that adjacent passes share.  Measured on
-// P39 64^3: FP64 K = 2 (96 VGPRs with whole-row waves, 5 waves/SIMD: 173 vs
-// 163 GDoF/s at K = 3), FP32 K = 2 (70 VGPRs, 7 waves/SIMD: 312 vs 298),
-// BF16 K = 3.
+// P39 64^3: FP64 K = 3 with whole-row waves held to 124 VGPRs (4
+// waves/SIMD: 176 GDoF/s; K = 2 at 96 VGPRs and 5 waves: 172), FP32 K = 2
+// (70 VGPRs, 7 waves/SIMD: 312 vs 298 at K = 3), BF16 K = 3.  The
+// transposed sweeps of FP64 run at K = 2 (PM_ADJ_K64).
 #ifndef PM_WIN_K64
-#define PM_WIN_K64 2
+#define PM_WIN_K64 3
+#endif
+#ifndef PM_ADJ_K64
+#define PM_ADJ_K64 2
 #endif
 #ifndef PM_WIN_K32
 #define PM_WIN_K32 2
@@ -429,8 +433,24 @@ enum SweepMode { kFwd = 0, kAdjTgt = 1, kAdjDual = 2 };
 // degree, grid) pair of the pass are formed once per cell from
 // c_l = mean sigma_a + (1 - g_l) mean sigma_s with the per-degree moments gl
 // and the substep length tau, and kept in LDS.
+// Resident waves per SIMD asked of the compiler for the whole-row forward
+// sweeps (register budget 512 / waves); 1 leaves the choice to it.
+#ifndef PM_WPE64
+#define PM_WPE64 4
+#endif
+#ifndef PM_WPE32
+#define PM_WPE32 1
+#endif
+#ifndef PM_WPE16
+#define PM_WPE16 1
+#endif
+template <class T> struct MinWaves { static constexpr int v = PM_WPE16; };
+template <> struct MinWaves<double> { static constexpr int v = PM_WPE64; };
+template <> struct MinWaves<float> { static constexpr int v = PM_WPE32; };
+
 template <class T, int K, int TPB, int CPL, int MODE, bool ANI, bool XROT>
-__global__ void __launch_bounds__(TPB) k_sweep_win(const T* __restrict__ us, T* __restrict__ u,
+__global__ void __launch_bounds__(TPB, (MODE == kFwd && XROT && !ANI) ? MinWaves<T>::v : 1)
+k_sweep_win(const T* __restrict__ us, T* __restrict__ u,
                                                    T* __restrict__ uw, double* __restrict__ gp,
                                                    const double* __restrict__ tab,
                                                    const int2* __restrict__ src,
@@ -727,6 +747,7 @@ __global__ void __launch_bounds__(TPB) k_sweep_win(const T* __restrict__ us, T* 
 }
 
 int win_depth(int prec) { return prec == kF64 ? PM_WIN_K64 : prec == kF32 ? PM_WIN_K32 : PM_WIN_K16; }
+int adj_depth(int prec) { return prec == kF64 ? PM_ADJ_K64 : prec == kF32 ? PM_WIN_K32 : PM_WIN_K16; }
 
 
 // Launch shape, measured on P39 64^3.  Cells per lane: 1 for FP64 and FP32
@@ -826,9 +847,9 @@ static void launch_adj_t(int side, const void* us, void* lam, void* w, double* g
 hipError_t launch_adj_win(int prec, int side, const void* us, void* lam, void* w, double* gp,
                           const double* tab, int rowbase, Aniso an, WinArgs a, GridDesc g,
                           hipStream_t st) {
-    if (a.K != win_depth(prec) || prec == kBF16) return hipErrorInvalidValue;
+    if (a.K != adj_depth(prec) || prec == kBF16) return hipErrorInvalidValue;
     if (prec == kF64)
-        launch_adj_t<double, PM_WIN_K64>(side, us, lam, w, gp, tab, rowbase, an, a, g, st);
+        launch_adj_t<double, PM_ADJ_K64>(side, us, lam, w, gp, tab, rowbase, an, a, g, st);
     else
         launch_adj_t<float, PM_WIN_K32>(side, us, lam, w, gp, tab, rowbase, an, a, g, st);
     return hipGetLastError();
