@@ -169,7 +169,7 @@ def ceilings(ncell):
     lib = ctypes.CDLL(os.path.join(ROOT, "paper_2004_02833_amd", "libpm_probe.so"))
     lib.pmp_ceilings.argtypes = [ctypes.c_longlong, ctypes.c_longlong, ctypes.POINTER(ctypes.c_double)]
     out = (ctypes.c_double * 4)()
-    rc = lib.pmp_ceilings(2 << 30, (ncell // 256) * 256, out)
+    rc = lib.pmp_ceilings(4 << 30, (ncell // 256) * 256, out)
     if rc != 0:
         return {"error": rc}
     return {"flat_read": round(out[0], 1), "flat_copy": round(out[1], 1),
@@ -217,15 +217,16 @@ def adjoint_timing(pm):
             "forward_ms": round((t1 - t0) * 1e3, 2), "grad_ms": round((t2 - t1) * 1e3, 2)}
 
 
-def cpu_baseline(w, steps):
+def cpu_baseline(w, steps, threads=0):
+    """The C oracle on the host: every core (threads=0) or the given count."""
     from oracle import c_oracle
     c_oracle.build(force=False)
     u0 = w.initial()
-    threads = c_oracle.threads()
     t0 = time.perf_counter()
-    c_oracle.run(w.N, w.shape, w.h, w.dt, w.sigma_a, w.sigma_s, w.q, u0, steps,
+    c_oracle.run(w.N, w.shape, w.h, w.dt, w.sigma_a, w.sigma_s, w.q, u0, steps, threads=threads,
                  scattering=w.extra.get("scattering"))
     dt = time.perf_counter() - t0
+    threads = c_oracle.threads()
     return {"value": round(w.n ** 3 * w.V * steps / dt / 1e9, 5), "unit": "GDoF-updates/s",
             "cores": threads, "kind": "oracle",
             "sample": "%d of %d steps of %s (P%d, %d^3), plain C/OpenMP FP64, %.1f s"
@@ -239,6 +240,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="p39_smooth")
     ap.add_argument("--cpu-steps", type=int, default=8)
+    ap.add_argument("--cpu-steps-1thread", type=int, default=1,
+                    help="steps of the one-thread oracle sample (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--forms", default="fp64,fp32",
                     help="storage forms to time; the first is the headline value")
@@ -247,7 +250,7 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true", help="skip the gradient timing")
     ap.add_argument("--no-ceilings", action="store_true",
                     help="skip the bandwidth ceilings (libpm_probe.so)")
-    ap.add_argument("--copy-gib", type=float, default=2.0,
+    ap.add_argument("--copy-gib", type=float, default=4.0,
                     help="size of the calibration copy (0: skip)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -303,12 +306,15 @@ def main():
         say("bench: adjoint timing")
         adjoint = adjoint_timing(pm)
 
-    cpu = None
+    cpu = cpu1 = None
     if not args.no_cpu_baseline and w.n ** 3 * w.V > 1_000_000_000:
         say("bench: cpu oracle sample skipped for %s (host memory)" % w.name)
     elif not args.no_cpu_baseline:
         say("bench: cpu oracle sample (%d steps)" % args.cpu_steps)
         cpu = cpu_baseline(w, args.cpu_steps)
+        if args.cpu_steps_1thread > 0:
+            say("bench: cpu oracle sample on one thread (%d steps)" % args.cpu_steps_1thread)
+            cpu1 = cpu_baseline(w, args.cpu_steps_1thread, threads=1)
 
     out = {
         "metric": "GDoF-updates/s (cell x moment per step) P39 3D; % HBM peak; FP32 vs FP64 error",
@@ -332,6 +338,7 @@ def main():
         "forms": {f: r for f, r in results.items() if f != forms[0]},
         "adjoint": adjoint,
         "cpu_baseline": cpu,
+        "cpu_baseline_1thread": cpu1,
         "paper_context": "139.1 MLCUP/s = 0.139 GDoF-updates/s per core, P39 FP64, Haswell Xeon "
                          "E5-2623 v3 (kasper), optimised AVX2 sweeps; other machine, context only",
         "copy_ceiling": copy,

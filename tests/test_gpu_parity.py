@@ -284,3 +284,19 @@ def test_rectangular_cells(N, shape, h):
         finally:
             pm.pm_finalize()
         assert relerr(got, ref) <= tol, prec
+
+
+@pytest.mark.parametrize("shape", [(3, 5, 64), (2, 3, 128), (5, 2, 64)])
+def test_whole_row_waves(shape):
+    """Rows of 64 cells (FP64, FP32) or 128 cells (BF16, two per lane) are
+    held by one wave, whose x neighbours come by lane rotation, periodic
+    wrap included; other row lengths load them.  All three forms against
+    the oracle, P7 (every staggering combination of sources and targets)."""
+    N = 7
+    sa, ss, q, u = rand_problem(N, shape, 51)
+    h, dt = 0.1, 0.04
+    ref = st.run(st.Setup(N, shape, h, dt, sa, ss, q), u, 3)
+    for prec, tol in ((pm.PM_FP64, 1e-13), (pm.PM_FP32, FP32_TOL), (pm.PM_BF16, 2e-2)):
+        e = relerr(gpu_run(N, shape, h, dt, sa, ss, q, u, 3, prec=prec), ref)
+        say("whole rows %s prec %d err %.2e" % (shape, prec, e))
+        assert e <= tol, prec
