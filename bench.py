@@ -45,11 +45,16 @@ def sweep_bytes(N, ncell, esz, parity):
 
 
 def kernel_source_hash():
+    """Hash of the device sources with comments and whitespace removed, so
+    that only code changes invalidate recorded counter data."""
+    import re
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_2004_02833_amd", "csrc")
     for name in sorted(os.listdir(d)):
         if name.endswith((".hip", ".h")) and name != "probe.hip":
-            h.update(open(os.path.join(d, name), "rb").read())
+            text = open(os.path.join(d, name)).read()
+            text = re.sub(r"//[^\n]*", "", text)
+            h.update(re.sub(r"\s+", "", text).encode())
     return h.hexdigest()[:16]
 
 

@@ -2,9 +2,11 @@
 //
 // State layout in HBM: moment-major planes, u[slot][z][y][x] with x fastest;
 // slots are grouped by staggered grid (G111, G221, G212, G122 | G211, G121,
-// G112, G222) so that each parity is one contiguous range.  One lane owns
-// one cell; a wave of 64 lanes covers 64 consecutive cells, so every plane
-// access of a wave is a contiguous 256 B (fp32) or 512 B (fp64) segment.
+// G112, G222) so that each parity is one contiguous range.  A lane owns CPL
+// consecutive cells of a row (1 for FP64 and FP32, 2 for BF16), so every
+// plane access of a wave is a contiguous segment of 64 CPL cells: 512 B
+// (FP64), 256 B (FP32, BF16).  Rows of exactly 64 CPL cells are held by one
+// wave each, whose x neighbours then come by lane rotation.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -428,13 +430,9 @@ __device__ __forceinline__ long long tile_cell(const TileMap& m, long long tile,
 //            backward one, so this is a forward-shaped stencil over w)
 enum SweepMode { kFwd = 0, kAdjTgt = 1, kAdjDual = 2 };
 
-// ANI (anisotropic scattering): the table rows of the four target grids hold
-// the means of sigma_a and sigma_s; the decay factors of every (target
-// degree, grid) pair of the pass are formed once per cell from
-// c_l = mean sigma_a + (1 - g_l) mean sigma_s with the per-degree moments gl
-// and the substep length tau, and kept in LDS.
 // Resident waves per SIMD asked of the compiler for the whole-row forward
-// sweeps (register budget 512 / waves); 1 leaves the choice to it.
+// sweeps (register budget 512 / waves, checked free of spills); 1 leaves the
+// choice to it.
 #ifndef PM_WPE64
 #define PM_WPE64 4
 #endif
@@ -448,18 +446,21 @@ template <class T> struct MinWaves { static constexpr int v = PM_WPE16; };
 template <> struct MinWaves<double> { static constexpr int v = PM_WPE64; };
 template <> struct MinWaves<float> { static constexpr int v = PM_WPE32; };
 
+// One kernel for the forward substep and both halves of its transpose.
+// ANI (anisotropic scattering): the table rows of the four target grids hold
+// the means of sigma_a and sigma_s; the decay factors of every (target
+// degree, grid) pair of the pass are formed once per cell from
+// c_l = mean sigma_a + (1 - g_l) mean sigma_s with the per-degree moments gl
+// and the substep length tau, and kept in LDS.  XROT: whole-row waves (see
+// win_fetch).
 template <class T, int K, int TPB, int CPL, int MODE, bool ANI, bool XROT>
 __global__ void __launch_bounds__(TPB, (MODE == kFwd && XROT && !ANI) ? MinWaves<T>::v : 1)
-k_sweep_win(const T* __restrict__ us, T* __restrict__ u,
-                                                   T* __restrict__ uw, double* __restrict__ gp,
-                                                   const double* __restrict__ tab,
-                                                   const int2* __restrict__ src,
-                                                   const int2* __restrict__ tgt,
-                                                   const typename Acc<T>::type* __restrict__ coef,
-                                                   const double* __restrict__ gl, double tau,
-                                                   int rowbase, int N, int parity, int npass,
-                                                   int per_xcd, long long ntile, TileMap tm,
-                                                   GridDesc g) {
+k_sweep_win(const T* __restrict__ us, T* __restrict__ u, T* __restrict__ uw,
+            double* __restrict__ gp, const double* __restrict__ tab,
+            const int2* __restrict__ src, const int2* __restrict__ tgt,
+            const typename Acc<T>::type* __restrict__ coef, const double* __restrict__ gl,
+            double tau, int rowbase, int N, int parity, int npass, int per_xcd, long long ntile,
+            TileMap tm, GridDesc g) {
     static_assert(MODE == kFwd || CPL == 1, "transposed sweeps use one cell per lane");
     static_assert(!(ANI && MODE == kAdjDual), "the dual side reads no decay factors");
     static_assert(!XROT || MODE == kFwd, "row rotation only in the forward sweep");
