@@ -19,8 +19,9 @@
 // re-reading the source degree that adjacent passes share.  Measured on
 // P39 64^3: FP64 K = 3 with whole-row waves held to 124 VGPRs (4
 // waves/SIMD: 176 GDoF/s; K = 2 at 96 VGPRs and 5 waves: 172), FP32 K = 2
-// (70 VGPRs, 7 waves/SIMD: 312 vs 298 at K = 3), BF16 K = 3.  The
-// transposed sweeps of FP64 run at K = 2 (PM_ADJ_K64).
+// where waves hold whole rows (62 VGPRs, 7 waves/SIMD: 312 vs 298 at K = 3)
+// and K = 3 otherwise (P39 160^3: 306 vs 291 at K = 2), BF16 K = 3.  The
+// transposed sweeps run at K = 2 (PM_ADJ_K64, PM_WIN_K32).
 #ifndef PM_WIN_K64
 #define PM_WIN_K64 3
 #endif
@@ -29,6 +30,9 @@
 #endif
 #ifndef PM_WIN_K32
 #define PM_WIN_K32 2
+#endif
+#ifndef PM_WIN_K32R
+#define PM_WIN_K32R 3
 #endif
 #ifndef PM_WIN_K16
 #define PM_WIN_K16 3
@@ -747,7 +751,11 @@ k_sweep_win(const T* __restrict__ us, T* __restrict__ u, T* __restrict__ uw,
     }
 }
 
-int win_depth(int prec) { return prec == kF64 ? PM_WIN_K64 : prec == kF32 ? PM_WIN_K32 : PM_WIN_K16; }
+int win_depth(int prec, int nx) {
+    if (prec == kF64) return PM_WIN_K64;
+    if (prec == kF32) return nx == 64 ? PM_WIN_K32 : PM_WIN_K32R;  // one cell per lane
+    return PM_WIN_K16;
+}
 int adj_depth(int prec) { return prec == kF64 ? PM_ADJ_K64 : prec == kF32 ? PM_WIN_K32 : PM_WIN_K16; }
 
 
@@ -758,9 +766,6 @@ int adj_depth(int prec) { return prec == kF64 ? PM_ADJ_K64 : prec == kF32 ? PM_W
 // faster in FP64 and slower in FP32.
 #ifndef PM_CPL64
 #define PM_CPL64 1
-#endif
-#ifndef PM_CPL32
-#define PM_CPL32 1
 #endif
 #ifndef PM_CPL16
 #define PM_CPL16 2
@@ -809,7 +814,7 @@ static void launch_fwd(void* u, const double* tab, int rowbase, Aniso an, WinArg
 
 hipError_t launch_sweep_win(int prec, void* u, const double* tab, int rowbase, Aniso an,
                             WinArgs a, GridDesc g, hipStream_t st) {
-    if (a.K != win_depth(prec)) return hipErrorInvalidValue;
+    if (a.K != win_depth(prec, g.nx)) return hipErrorInvalidValue;
     // several cells per lane need whole lane groups within every row
     if (prec == kF64) {
         if (PM_CPL64 > 1 && g.nx % PM_CPL64 == 0)
@@ -817,10 +822,10 @@ hipError_t launch_sweep_win(int prec, void* u, const double* tab, int rowbase, A
         else
             launch_fwd<double, PM_WIN_K64, 1>(u, tab, rowbase, an, a, g, st);
     } else if (prec == kF32) {
-        if (PM_CPL32 > 1 && g.nx % PM_CPL32 == 0)
-            launch_fwd<float, PM_WIN_K32, PM_CPL32>(u, tab, rowbase, an, a, g, st);
-        else
+        if (a.K == PM_WIN_K32)
             launch_fwd<float, PM_WIN_K32, 1>(u, tab, rowbase, an, a, g, st);
+        else
+            launch_fwd<float, PM_WIN_K32R, 1>(u, tab, rowbase, an, a, g, st);
     } else {
         if (PM_CPL16 > 1 && g.nx % PM_CPL16 == 0)
             launch_fwd<bf16s, PM_WIN_K16, PM_CPL16>(u, tab, rowbase, an, a, g, st);
