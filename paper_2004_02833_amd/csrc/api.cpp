@@ -54,6 +54,7 @@ struct Ctx {
     size_t esz = 8;
     pm::GridDesc g{};
     pm::Layout L;
+    long long ve = 0;  // planes of the even parity (slots [0, ve)); odd ones follow
     void* u = nullptr;
     double* tab = nullptr;
     double* sig = nullptr;  // sigma_a, sigma_s (device copies)
@@ -78,6 +79,8 @@ struct Ctx {
     long long base_bytes = 0;
 
     size_t state_bytes() const { return (size_t)V * (size_t)g.pstride * esz; }
+    // element offset of the first plane of a parity within a state
+    long long half(int parity) const { return parity ? ve * g.pstride : 0; }
     hipStream_t stream() const { return g_bound ? g_bound : own; }
     void* plane(void* base, int slot) const {
         return (char*)base + (size_t)slot * (size_t)g.pstride * esz;
@@ -196,7 +199,8 @@ int build_window_tables(int K, pm::WinArgs (&win)[2], void** mem) {
                         if (!exists(ls, mu, ty)) continue;
                         const int j = idx(ls, mu, ty);
                         const int bits = pm::grid_bits(ls, ty == 0 ? mu : -mu);
-                        h.src[((size_t)(pass * MU1 + mu) * (K + 1) + b) * 2 + ty] = make_int2(L.slot_of[j], bits);
+                        h.src[((size_t)(pass * MU1 + mu) * (K + 1) + b) * 2 + ty] =
+                            make_int2(L.slot_of[j] - (p ? 0 : (int)C.ve), bits);
                         for (int side = 0; side < 2; ++side) {
                             const int t = side == 0 ? b : b - 1;
                             if (t < 0 || t >= K) continue;
@@ -223,13 +227,20 @@ int build_window_tables(int K, pm::WinArgs (&win)[2], void** mem) {
                         if (!exists(lt, mu, ty)) continue;
                         const int i = idx(lt, mu, ty);
                         const int row = i == 0 ? pm::kTabMom0 : 2 * L.order_of[i];
-                        h.tgt[((size_t)(pass * MU1 + mu) * K + t) * 2 + ty] = make_int2(L.slot_of[i], row);
+                        h.tgt[((size_t)(pass * MU1 + mu) * K + t) * 2 + ty] =
+                            make_int2(L.slot_of[i] - (p ? (int)C.ve : 0), row);
                     }
             }
         }
         if (used != nnz_par[p])
             return fail(PM_EINVAL, "internal: window streams cover " + std::to_string(used) + " of " +
                                        std::to_string(nnz_par[p]) + " couplings");
+        // slots count from the first plane of their parity half
+        const long long nhalf[2] = {C.ve, (long long)V - C.ve};
+        for (const int2& e : h.src)
+            if (e.x >= nhalf[1 - p]) return fail(PM_EINVAL, "internal: source slot outside its half");
+        for (const int2& e : h.tgt)
+            if (e.x >= nhalf[p]) return fail(PM_EINVAL, "internal: target slot outside its half");
     }
     const bool f64 = C.prec == PM_FP64;
     const size_t es = f64 ? sizeof(double) : sizeof(float);
@@ -276,7 +287,8 @@ int sweep(void* u, int parity, bool full = false) {
     const double tau = parity == 0 || full ? C.dt : 0.5 * C.dt;
     const int rowbase = parity == 0 ? 0 : full && !C.aniso ? pm::kTabOddFull : 8;
     const pm::Aniso an{C.aniso ? C.gl : nullptr, tau};
-    HIPCHK(pm::launch_sweep_win(C.prec, u, C.tab, rowbase, an, C.win[parity], C.g, C.stream()));
+    const pm::StateOffs so{C.half(1 - parity), C.half(parity), C.half(parity), 0, 0};
+    HIPCHK(pm::launch_sweep_win(C.prec, u, so, C.tab, rowbase, an, C.win[parity], C.g, C.stream()));
     if (C.timing) {
         HIPCHK(hipEventRecord(b, C.stream()));
         C.ev[parity].push_back({a, b});
@@ -387,6 +399,8 @@ int pm_init_cells(int N, int nx, int ny, int nz, double dx, double dy, double dz
     C.g.ncell = ncell;
     C.g.pstride = plane_stride(ncell);
     C.L = pm::make_layout(N);
+    C.ve = 0;
+    for (int l = 0; l <= N; l += 2) C.ve += 2 * l + 1;
     std::vector<double> gl(N + 1, 0.0);
     gl[0] = 1.0;
     for (int l = 1; l <= N && l - 1 < (int)g_pending_scat.size(); ++l) gl[l] = g_pending_scat[l - 1];
@@ -555,6 +569,13 @@ int pm_set_checkpoint(int k) {
     return PM_OK;
 }
 
+// Reverse pass.  One pool holds lam, w and the states of a segment as
+// parity halves: a substep writes the new half of its own parity into a fresh
+// buffer and shares the other half with its input, so the recomputation of a
+// segment keeps every intermediate substep state without copies.  For step
+// j of a segment with state (E_j, O_j): O'_j = S^o half step, E'_j = S^e,
+// O''_j = S^o again, and state j + 1 = (E'_j, O''_j).  The transposes then
+// run on (E'_j, O'_j), (E_j, O'_j) and (E_j, O_j).
 int pm_grad(const double* dL_du0, double* dsa, double* dss) {
     if (!C.live) return fail(PM_ESTATE, "no context: call pm_init first");
     if (C.ck <= 0) return fail(PM_ESTATE, "no gradient recording: call pm_set_checkpoint(k > 0) before pm_step");
@@ -564,13 +585,19 @@ int pm_grad(const double* dL_du0, double* dsa, double* dss) {
     const long long n = C.ncell;
     const long long T = C.rec_steps;
     const int ck = C.ck;
-    void *lam = nullptr, *w = nullptr, *ua = nullptr, *ub = nullptr, *seg = nullptr;
+    const long long ps = C.g.pstride;
+    const long long SE = (long long)C.V * ps;      // elements of a state
+    const long long EH = C.ve * ps;                 // elements of the even half
+    const long long OH = SE - EH;                   // elements of the odd half
+    const long long region = 2 * OH + EH;           // O', E', O'' of one step
+    const int segs = T > 0 ? (int)std::min<long long>(ck, T) : 1;
+    const long long pool_elems = 3 * SE + (long long)segs * region;
+    void* pool = nullptr;
     double *grad = nullptr, *outg = nullptr, *gpass = nullptr;
     const long long before = C.dev_bytes;
     const bool timing = C.timing;
     auto cleanup = [&]() {
-        dfree(lam); dfree(w); dfree(ua); dfree(ub); dfree(seg); dfree(grad); dfree(outg);
-        dfree(gpass);
+        dfree(pool); dfree(grad); dfree(outg); dfree(gpass);
         C.dev_bytes = before;
         C.timing = timing;
     };
@@ -591,62 +618,73 @@ int pm_grad(const double* dL_du0, double* dsa, double* dss) {
             return fail(PM_EDEVICE, std::string(#x) + ": " + hipGetErrorString(e_));   \
         }                                                                              \
     } while (0)
-    const int segs = T > 0 ? ck : 1;
     const int np0 = C.wadj[0].npass, np1 = C.wadj[1].npass;
     const size_t gpb = sizeof(double) * pm::kGradRows * (size_t)n;  // one pass of gradient rows
+    const size_t pool_bytes = C.esz * (size_t)pool_elems;
     {
         size_t fr = 0, tot = 0;
         HIPCHK(hipMemGetInfo(&fr, &tot));
-        const size_t need = SB * (size_t)(4 + segs) + gpb * (size_t)(np0 + np1 + 1) +
-                            sizeof(double) * 2 * (size_t)n;
+        const size_t need = pool_bytes + gpb * (size_t)(np0 + np1 + 1) + sizeof(double) * 2 * (size_t)n;
         if (need > fr)
             return fail(PM_ENOMEM, "gradient pass needs " + std::to_string(need) + " bytes, " +
                                        std::to_string(fr) + " free on the device");
     }
-    TRYG(dmalloc(&lam, SB, "adjoint state"));
-    TRYG(dmalloc(&w, SB, "adjoint work"));
-    TRYG(dmalloc(&ua, SB, "recompute a"));
-    TRYG(dmalloc(&ub, SB, "recompute b"));
-    TRYG(dmalloc(&seg, SB * (size_t)segs, "segment states"));
+    TRYG(dmalloc(&pool, pool_bytes, "adjoint and segment states"));
     TRYG(dmalloc(&gpass, gpb * (size_t)(np0 + np1), "per-pass gradient rows"));
     TRYG(dmalloc(&grad, gpb, "gradient accumulators"));
     TRYG(dmalloc(&outg, sizeof(double) * 2 * (size_t)n, "gradient output"));
-    HIPG(pm::launch_fill_zero(lam, (long long)SB, s));
-    HIPG(pm::launch_fill_zero(w, (long long)SB, s));
+    // pool layout (elements): lam [0, SE), w [SE, 2 SE), segment start state
+    // [2 SE, 3 SE), then one region per step
+    const long long LAM = 0, W = SE, START = 2 * SE;
+    auto reg = [&](long long j) { return 3 * SE + j * region; };
+    auto Ej = [&](long long j) { return j == 0 ? START : reg(j - 1) + OH; };
+    auto Oj = [&](long long j) { return j == 0 ? START + EH : reg(j - 1) + OH + EH; };
+    auto O1 = [&](long long j) { return reg(j); };
+    auto E1 = [&](long long j) { return reg(j) + OH; };
+    auto O2 = [&](long long j) { return reg(j) + OH + EH; };
+    HIPG(pm::launch_fill_zero(pool, (long long)(C.esz * (size_t)SE), s));
     HIPG(pm::launch_fill_zero(gpass, (long long)(gpb * (np0 + np1)), s));
     HIPG(hipMemcpyAsync(C.plane64, dL_du0, sizeof(double) * n, hipMemcpyHostToDevice, s));
-    HIPG(pm::launch_from_f64(C.prec, C.plane64, C.plane(lam, C.L.slot_of[0]), n, s));
+    HIPG(pm::launch_from_f64(C.prec, C.plane64, C.plane(pool, C.L.slot_of[0]), n, s));
     double* gp_par[2] = {gpass, gpass + (size_t)np0 * pm::kGradRows * (size_t)n};
     C.timing = false;
+    auto fwd = [&](int p, long long src, long long tin, long long tout) -> hipError_t {
+        if (C.win[p].npass == 0) return hipSuccess;  // a parity without moments (N = 0, odd)
+        const pm::Aniso an{C.aniso ? C.gl : nullptr, p ? 0.5 * C.dt : C.dt};
+        return pm::launch_sweep_win(C.prec, pool, pm::StateOffs{src, tin, tout, 0, 0}, C.tab,
+                                    p ? 8 : 0, an, C.win[p], C.g, s);
+    };
+    // transpose of the substep of parity p whose old state has halves (E, O)
+    auto adj = [&](int p, long long E, long long O) -> hipError_t {
+        const pm::Aniso an{C.aniso ? C.gl : nullptr, p ? 0.5 * C.dt : C.dt};
+        const long long lam_t = LAM + (p ? EH : 0), lam_d = LAM + (p ? 0 : EH);
+        const long long w_t = W + (p ? EH : 0);
+        if (C.wadj[p].npass > 0) {
+            const pm::StateOffs so{p ? E : O, lam_t, lam_t, p ? O : E, w_t};
+            hipError_t e = pm::launch_adj_win(C.prec, 0, pool, so, gp_par[p], C.tab, p ? 8 : 0, an,
+                                              C.wadj[p], C.g, s);
+            if (e != hipSuccess) return e;
+        }
+        if (C.wadj[1 - p].npass > 0) {
+            const pm::StateOffs so{w_t, lam_d, lam_d, 0, 0};
+            return pm::launch_adj_win(C.prec, 1, pool, so, nullptr, C.tab, 0, an, C.wadj[1 - p],
+                                      C.g, s);
+        }
+        return hipSuccess;
+    };
     const long long nseg = (T + ck - 1) / ck;
     for (long long gseg = nseg - 1; gseg >= 0; --gseg) {
-        const long long s0 = gseg * ck, s1 = std::min<long long>(s0 + ck, T);
-        char* sb = (char*)seg;
-        HIPG(hipMemcpyAsync(sb, C.ckpts[gseg], SB, hipMemcpyDeviceToDevice, s));
-        for (long long k = s0 + 1; k < s1; ++k) {
-            void* dst = sb + (size_t)(k - s0) * SB;
-            HIPG(hipMemcpyAsync(dst, sb + (size_t)(k - s0 - 1) * SB, SB, hipMemcpyDeviceToDevice, s));
-            TRYG(full_step(dst));
+        const long long s0 = gseg * ck, len = std::min<long long>(s0 + ck, T) - s0;
+        HIPG(hipMemcpyAsync((char*)pool + C.esz * START, C.ckpts[gseg], SB, hipMemcpyDeviceToDevice, s));
+        for (long long j = 0; j < len; ++j) {
+            HIPG(fwd(1, Ej(j), Oj(j), O1(j)));
+            HIPG(fwd(0, O1(j), Ej(j), E1(j)));
+            if (j + 1 < len) HIPG(fwd(1, E1(j), O1(j), O2(j)));
         }
-        for (long long k = s1 - 1; k >= s0; --k) {
-            void* un = sb + (size_t)(k - s0) * SB;
-            HIPG(hipMemcpyAsync(ua, un, SB, hipMemcpyDeviceToDevice, s));
-            TRYG(sweep(ua, 1));
-            HIPG(hipMemcpyAsync(ub, ua, SB, hipMemcpyDeviceToDevice, s));
-            TRYG(sweep(ub, 0));
-            // transposes of S^o (on ub), S^e (on ua), S^o (on un), in that order
-            const void* olds[3] = {ub, ua, un};
-            const int pars[3] = {1, 0, 1};
-            for (int j = 0; j < 3; ++j) {
-                const int p = pars[j];
-                const pm::Aniso an{C.aniso ? C.gl : nullptr, p ? 0.5 * C.dt : C.dt};
-                if (C.wadj[p].npass > 0)
-                    HIPG(pm::launch_adj_win(C.prec, 0, olds[j], lam, w, gp_par[p], C.tab,
-                                            p ? 8 : 0, an, C.wadj[p], C.g, s));
-                if (C.wadj[1 - p].npass > 0)
-                    HIPG(pm::launch_adj_win(C.prec, 1, w, lam, nullptr, nullptr, C.tab, 0, an,
-                                            C.wadj[1 - p], C.g, s));
-            }
+        for (long long j = len - 1; j >= 0; --j) {
+            HIPG(adj(1, E1(j), O1(j)));  // the closing odd half step
+            HIPG(adj(0, Ej(j), O1(j)));  // the even step
+            HIPG(adj(1, Ej(j), Oj(j)));  // the opening odd half step
         }
     }
     HIPG(pm::launch_grad_sum(gpass, np0 + np1, grad, n, s));

@@ -31,6 +31,8 @@ struct GridDesc {
 // passes of K target degrees; pass p, source column mu (0 <= mu <= N + 1)
 // is described by host-built streams, in the order the kernel consumes them:
 //   src[((p * MU1 + mu) * (K + 1) + b) * 2 + ty] = {slot or -1, parity bits}
+//       (slots count from the first plane of the dual parity; targets from
+//       the first plane of the sweep's parity)
 //       source degree L0 - 1 + 2b, m = +mu (ty 0, cos) or -mu (ty 1, sin);
 //   tgt[((p * MU1 + mu) * K + t) * 2 + ty] = {slot or -1, alpha table row}
 //       target degree L0 + 2t, m = +-mu;
@@ -69,19 +71,30 @@ struct Aniso {
 hipError_t launch_tables(const double* sa, const double* ss, const double* q, double* tab,
                          GridDesc g, double dt, bool aniso, hipStream_t st);
 
+// Planes of a sweep, as element offsets from one base pointer (the pool):
+// src = first plane of the dual parity (the sources), tin / tout = first
+// target plane read / written (equal for an update in place); for the
+// target side of the transpose also aux = first target plane of the old
+// state and w = first plane of the output beta * lam.  Slot numbers in the
+// streams count from the first plane of their parity.
+struct StateOffs {
+    long long src, tin, tout, aux, w;
+};
+
 // rowbase: table row of alpha for the first target grid of the parity
 // (0 for the even sweep, 8 for an odd half step, kTabOddFull for a full one;
 // with anisotropic scattering 0 or 8, the substep length coming from an.tau).
-hipError_t launch_sweep_win(int prec, void* u, const double* tab, int rowbase, Aniso an,
-                            WinArgs a, GridDesc g, hipStream_t st);
+hipError_t launch_sweep_win(int prec, void* pool, StateOffs so, const double* tab, int rowbase,
+                            Aniso an, WinArgs a, GridDesc g, hipStream_t st);
 
-// Transposed substep on the window streams.  side 0 (target side): us = old
-// state, lam = cotangent (targets updated), w = output beta * lam, gp =
-// per-pass gradient rows of this parity ([npass][kGradRows][ncell], added
-// to).  side 1 (dual side): us = w, lam updated on the dual moments.
-// FP64 and FP32 only.  With anisotropic scattering the gradient rows 2s and
-// 2s + 1 are dL/d(mean sigma_a) and dL/d(mean sigma_s) of grid s.
-hipError_t launch_adj_win(int prec, int side, const void* us, void* lam, void* w, double* gp,
+// Transposed substep on the window streams.  side 0 (target side): so.src /
+// so.aux = dual / target half of the old state, tin = tout = cotangent lam
+// of the targets (updated), w = output beta * lam, gp = per-pass gradient
+// rows of this parity ([npass][kGradRows][ncell], added to).  side 1 (dual
+// side): src = the w half, tin = tout = lam of the dual moments.  FP64 and
+// FP32 only.  With anisotropic scattering the gradient rows 2s and 2s + 1
+// are dL/d(mean sigma_a) and dL/d(mean sigma_s) of grid s.
+hipError_t launch_adj_win(int prec, int side, void* pool, StateOffs so, double* gp,
                           const double* tab, int rowbase, Aniso an, WinArgs a, GridDesc g,
                           hipStream_t st);
 hipError_t launch_grad_sum(const double* gp, int nbuf, double* grad, long long n, hipStream_t st);

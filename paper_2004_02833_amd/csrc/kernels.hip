@@ -425,7 +425,8 @@ __device__ __forceinline__ long long tile_cell(const TileMap& m, long long tile,
 // Finalisation modes of the window sweep:
 //   kFwd     substep of eq. (5): u_i <- alpha u_i + beta (q_i - S_i)
 //   kAdjTgt  transpose, target side: with lam_i the cotangent of the updated
-//            u_i and S_i recomputed from the old state (sources us), add
+//            u_i and S_i recomputed from the old state (its dual half at
+//            so.src, its target half at so.aux), add
 //            lam_i u_i and lam_i (q_i - S_i) to the gradients of alpha and
 //            beta of the target's coefficient set, write w_i = beta lam_i
 //            and lam_i <- alpha lam_i
@@ -449,6 +450,19 @@ enum SweepMode { kFwd = 0, kAdjTgt = 1, kAdjDual = 2 };
 template <class T> struct MinWaves { static constexpr int v = PM_WPE16; };
 template <> struct MinWaves<double> { static constexpr int v = PM_WPE64; };
 template <> struct MinWaves<float> { static constexpr int v = PM_WPE32; };
+// and for the FP64 transposed sweeps (target side, dual side)
+#ifndef PM_WPE64_ADJ
+#define PM_WPE64_ADJ 4
+#endif
+#ifndef PM_WPE64_DUAL
+#define PM_WPE64_DUAL 4
+#endif
+template <class T, int MODE, bool ANI, bool XROT>
+constexpr int min_waves() {
+    if (MODE == kFwd) return XROT && !ANI ? MinWaves<T>::v : 1;
+    if (!std::is_same<T, double>::value || ANI) return 1;
+    return MODE == kAdjTgt ? PM_WPE64_ADJ : PM_WPE64_DUAL;
+}
 
 // One kernel for the forward substep and both halves of its transpose.
 // ANI (anisotropic scattering): the table rows of the four target grids hold
@@ -458,9 +472,9 @@ template <> struct MinWaves<float> { static constexpr int v = PM_WPE32; };
 // and the substep length tau, and kept in LDS.  XROT: whole-row waves (see
 // win_fetch).
 template <class T, int K, int TPB, int CPL, int MODE, bool ANI, bool XROT>
-__global__ void __launch_bounds__(TPB, (MODE == kFwd && XROT && !ANI) ? MinWaves<T>::v : 1)
-k_sweep_win(const T* __restrict__ us, T* __restrict__ u, T* __restrict__ uw,
-            double* __restrict__ gp, const double* __restrict__ tab,
+__global__ void __launch_bounds__(TPB, (min_waves<T, MODE, ANI, XROT>()))
+k_sweep_win(T* __restrict__ pool, StateOffs so, double* __restrict__ gp,
+            const double* __restrict__ tab,
             const int2* __restrict__ src, const int2* __restrict__ tgt,
             const typename Acc<T>::type* __restrict__ coef, const double* __restrict__ gl,
             double tau, int rowbase, int N, int parity, int npass, int per_xcd, long long ntile,
@@ -468,8 +482,11 @@ k_sweep_win(const T* __restrict__ us, T* __restrict__ u, T* __restrict__ uw,
     static_assert(MODE == kFwd || CPL == 1, "transposed sweeps use one cell per lane");
     static_assert(!(ANI && MODE == kAdjDual), "the dual side reads no decay factors");
     static_assert(!XROT || MODE == kFwd, "row rotation only in the forward sweep");
-    // the forward substep reads its sources from the state it updates
-    const T* __restrict__ sv = MODE == kFwd ? u : us;
+    // every plane is addressed from one base: sources (the dual parity),
+    // targets read and written (equal offsets for an update in place)
+    const T* sv = pool + so.src;
+    const T* tin = pool + so.tin;
+    T* tout = pool + so.tout;
     using A = typename Acc<T>::type;
     using V = typename Pack<T, CPL>::V;
     const int xcd = blockIdx.x % kXcds;
@@ -554,7 +571,7 @@ k_sweep_win(const T* __restrict__ us, T* __restrict__ u, T* __restrict__ uw,
 #pragma unroll
             for (int ty = 0; ty < 2; ++ty) {
                 const int2 dn = td[t * 2 + ty];
-                tpf[t][ty] = dn.x >= 0 ? __builtin_nontemporal_load((const V*)(u + (long long)dn.x * ps + nb.c0)) : V{};
+                tpf[t][ty] = dn.x >= 0 ? __builtin_nontemporal_load((const V*)(tin + (long long)dn.x * ps + nb.c0)) : V{};
             }
     }
     A S[3][K][2][CPL];        // partial sums: target columns mu-1, mu, mu+1
@@ -651,7 +668,7 @@ k_sweep_win(const T* __restrict__ us, T* __restrict__ u, T* __restrict__ uw,
                             const int2 dn = tdn[t * 2 + ty];
                             if (dn.x >= 0)
                                 tpf[t][ty] = __builtin_nontemporal_load(
-                                    (const V*)(u + (long long)dn.x * ps + nb.c0));
+                                    (const V*)(tin + (long long)dn.x * ps + nb.c0));
                         }
                 }
             }
@@ -664,12 +681,12 @@ k_sweep_win(const T* __restrict__ us, T* __restrict__ u, T* __restrict__ uw,
                     // moment 0 (row code kTabMom0) is grid G111, degree 0, under ANI
                     const int ra = ANI ? 2 * (4 * t + ((d.y >> 1) & 3))
                                        : d.y == kTabMom0 ? 8 : 2 * ((d.y >> 1) & 3);
-                    T* ut = u + (long long)d.x * ps + nb.c0;
+                    T* ut = tout + (long long)d.x * ps + nb.c0;
                     A old[CPL];
                     if constexpr (MODE == kFwd)
                         unpack<T, CPL, A>(tcur[t][ty], old);
                     else
-                        unpack<T, CPL, A>(__builtin_nontemporal_load((const V*)ut), old);
+                        unpack<T, CPL, A>(__builtin_nontemporal_load((const V*)(tin + (long long)d.x * ps + nb.c0)), old);
                     double nv[CPL];
                     if constexpr (MODE == kFwd) {
 #pragma unroll
@@ -683,7 +700,7 @@ k_sweep_win(const T* __restrict__ us, T* __restrict__ u, T* __restrict__ uw,
                     } else {
                         // old[0] is lam_i; the old u_i comes from the source state
                         const double lam = (double)old[0];
-                        const double uo = (double)ld(sv + (long long)d.x * ps + nb.c0);
+                        const double uo = (double)ld(pool + so.aux + (long long)d.x * ps + nb.c0);
                         const double q = d.y == kTabMom0 ? tl[kRowQ][tid] : 0.0;
                         const double r = q - (double)S[0][t][ty][0];
                         if constexpr (ANI) {
@@ -715,7 +732,7 @@ k_sweep_win(const T* __restrict__ us, T* __restrict__ u, T* __restrict__ uw,
                                 }
                         }
                         const double wv[1] = {tl[ra + 1][tid] * lam};
-                        if (live) st(uw + (long long)d.x * ps + nb.c0, wv[0]);
+                        if (live) st(pool + so.w + (long long)d.x * ps + nb.c0, wv[0]);
                         nv[0] = tl[ra][tid] * lam;
                     }
                     if (live) __builtin_nontemporal_store(pack<T, CPL>(nv), (V*)ut);
@@ -772,7 +789,7 @@ int adj_depth(int prec) { return prec == kF64 ? PM_ADJ_K64 : prec == kF32 ? PM_W
 #endif
 
 template <class T, int K, int CPL, int MODE, bool ANI>
-static void launch_win_t(const T* us, T* u, T* uw, double* gp, const double* tab, int rowbase,
+static void launch_win_t(T* pool, StateOffs so, double* gp, const double* tab, int rowbase,
                          Aniso an, WinArgs a, GridDesc g, hipStream_t st) {
     using A = typename Acc<T>::type;
     constexpr int TPB = 256 / CPL;
@@ -793,71 +810,65 @@ static void launch_win_t(const T* us, T* u, T* uw, double* gp, const double* tab
     // one whole row per wave: x neighbours by lane rotation
     if (MODE == kFwd && sw == g.nx && g.nx == 64 * CPL)
         hipLaunchKernelGGL((k_sweep_win<T, K, TPB, CPL, MODE, ANI, MODE == kFwd>), dim3(nwg),
-                           dim3(TPB), 0, st, us, u, uw, gp, tab, a.src, a.tgt, (const A*)a.coef,
+                           dim3(TPB), 0, st, pool, so, gp, tab, a.src, a.tgt, (const A*)a.coef,
                            an.gl, an.tau, rowbase, a.N, a.parity, a.npass, per_xcd, ntile, tm, g);
     else
         hipLaunchKernelGGL((k_sweep_win<T, K, TPB, CPL, MODE, ANI, false>), dim3(nwg), dim3(TPB),
-                           0, st, us, u, uw, gp, tab, a.src, a.tgt, (const A*)a.coef, an.gl,
+                           0, st, pool, so, gp, tab, a.src, a.tgt, (const A*)a.coef, an.gl,
                            an.tau, rowbase, a.N, a.parity, a.npass, per_xcd, ntile, tm, g);
 }
 
 template <class T, int K, int CPL>
-static void launch_fwd(void* u, const double* tab, int rowbase, Aniso an, WinArgs a, GridDesc g,
-                       hipStream_t st) {
+static void launch_fwd(void* pool, StateOffs so, const double* tab, int rowbase, Aniso an,
+                       WinArgs a, GridDesc g, hipStream_t st) {
     if (an.gl)
-        launch_win_t<T, K, CPL, kFwd, true>((const T*)u, (T*)u, nullptr, nullptr, tab, rowbase, an,
-                                            a, g, st);
+        launch_win_t<T, K, CPL, kFwd, true>((T*)pool, so, nullptr, tab, rowbase, an, a, g, st);
     else
-        launch_win_t<T, K, CPL, kFwd, false>((const T*)u, (T*)u, nullptr, nullptr, tab, rowbase,
-                                             an, a, g, st);
+        launch_win_t<T, K, CPL, kFwd, false>((T*)pool, so, nullptr, tab, rowbase, an, a, g, st);
 }
 
-hipError_t launch_sweep_win(int prec, void* u, const double* tab, int rowbase, Aniso an,
-                            WinArgs a, GridDesc g, hipStream_t st) {
+hipError_t launch_sweep_win(int prec, void* pool, StateOffs so, const double* tab, int rowbase,
+                            Aniso an, WinArgs a, GridDesc g, hipStream_t st) {
     if (a.K != win_depth(prec, g.nx)) return hipErrorInvalidValue;
     // several cells per lane need whole lane groups within every row
     if (prec == kF64) {
         if (PM_CPL64 > 1 && g.nx % PM_CPL64 == 0)
-            launch_fwd<double, PM_WIN_K64, PM_CPL64>(u, tab, rowbase, an, a, g, st);
+            launch_fwd<double, PM_WIN_K64, PM_CPL64>(pool, so, tab, rowbase, an, a, g, st);
         else
-            launch_fwd<double, PM_WIN_K64, 1>(u, tab, rowbase, an, a, g, st);
+            launch_fwd<double, PM_WIN_K64, 1>(pool, so, tab, rowbase, an, a, g, st);
     } else if (prec == kF32) {
         if (a.K == PM_WIN_K32)
-            launch_fwd<float, PM_WIN_K32, 1>(u, tab, rowbase, an, a, g, st);
+            launch_fwd<float, PM_WIN_K32, 1>(pool, so, tab, rowbase, an, a, g, st);
         else
-            launch_fwd<float, PM_WIN_K32R, 1>(u, tab, rowbase, an, a, g, st);
+            launch_fwd<float, PM_WIN_K32R, 1>(pool, so, tab, rowbase, an, a, g, st);
     } else {
         if (PM_CPL16 > 1 && g.nx % PM_CPL16 == 0)
-            launch_fwd<bf16s, PM_WIN_K16, PM_CPL16>(u, tab, rowbase, an, a, g, st);
+            launch_fwd<bf16s, PM_WIN_K16, PM_CPL16>(pool, so, tab, rowbase, an, a, g, st);
         else
-            launch_fwd<bf16s, PM_WIN_K16, 1>(u, tab, rowbase, an, a, g, st);
+            launch_fwd<bf16s, PM_WIN_K16, 1>(pool, so, tab, rowbase, an, a, g, st);
     }
     return hipGetLastError();
 }
 
 template <class T, int K>
-static void launch_adj_t(int side, const void* us, void* lam, void* w, double* gp,
-                         const double* tab, int rowbase, Aniso an, WinArgs a, GridDesc g,
-                         hipStream_t st) {
+static void launch_adj_t(int side, void* pool, StateOffs so, double* gp, const double* tab,
+                         int rowbase, Aniso an, WinArgs a, GridDesc g, hipStream_t st) {
     if (side == 1)
-        launch_win_t<T, K, 1, kAdjDual, false>((const T*)us, (T*)lam, nullptr, nullptr, tab, 0, an,
-                                               a, g, st);
+        launch_win_t<T, K, 1, kAdjDual, false>((T*)pool, so, nullptr, tab, 0, an, a, g, st);
     else if (an.gl)
-        launch_win_t<T, K, 1, kAdjTgt, true>((const T*)us, (T*)lam, (T*)w, gp, tab, rowbase, an, a,
-                                             g, st);
+        launch_win_t<T, K, 1, kAdjTgt, true>((T*)pool, so, gp, tab, rowbase, an, a, g, st);
     else
-        launch_win_t<T, K, 1, kAdjTgt, false>((const T*)us, (T*)lam, (T*)w, gp, tab, rowbase, an,
-                                              a, g, st);
+        launch_win_t<T, K, 1, kAdjTgt, false>((T*)pool, so, gp, tab, rowbase, an, a, g, st);
 }
 
-hipError_t launch_adj_win(int prec, int side, const void* us, void* lam, void* w, double* gp,
+hipError_t launch_adj_win(int prec, int side, void* pool, StateOffs so, double* gp,
                           const double* tab, int rowbase, Aniso an, WinArgs a, GridDesc g,
                           hipStream_t st) {
     if (a.K != adj_depth(prec) || prec == kBF16) return hipErrorInvalidValue;
     if (prec == kF64)
-        launch_adj_t<double, PM_ADJ_K64>(side, us, lam, w, gp, tab, rowbase, an, a, g, st);
+        launch_adj_t<double, PM_ADJ_K64>(side, pool, so, gp, tab, rowbase, an, a, g, st);
     else
-        launch_adj_t<float, PM_WIN_K32>(side, us, lam, w, gp, tab, rowbase, an, a, g, st);
+        launch_adj_t<float, PM_WIN_K32>(side, pool, so, gp, tab, rowbase, an, a, g, st);
     return hipGetLastError();
 }
 
