@@ -300,3 +300,18 @@ def test_whole_row_waves(shape):
         e = relerr(gpu_run(N, shape, h, dt, sa, ss, q, u, 3, prec=prec), ref)
         say("whole rows %s prec %d err %.2e" % (shape, prec, e))
         assert e <= tol, prec
+
+
+@pytest.mark.parametrize("shape", [(3, 4, 100), (2, 3, 130), (2, 2, 500)])
+def test_long_rows_linear_tiles(shape):
+    """Rows longer than a wave that no segment width of 16, 32 or 64 lanes
+    divides run on linear tiles, whose waves cross row ends (x neighbours
+    and the periodic wrap loaded per lane).  All three forms."""
+    N = 5
+    sa, ss, q, u = rand_problem(N, shape, 61)
+    h, dt = 0.1, 0.04
+    ref = st.run(st.Setup(N, shape, h, dt, sa, ss, q), u, 3)
+    for prec, tol in ((pm.PM_FP64, 1e-13), (pm.PM_FP32, FP32_TOL), (pm.PM_BF16, 2e-2)):
+        e = relerr(gpu_run(N, shape, h, dt, sa, ss, q, u, 3, prec=prec), ref)
+        say("long rows %s prec %d err %.2e" % (shape, prec, e))
+        assert e <= tol, prec
