@@ -112,7 +112,9 @@ int pm_write_dev(int moment, const void* device_src);
  * odd half step per step (adjacent odd half steps merged, see pm_set_merge),
  * queued on the bound stream without host synchronisation.  When a gradient
  * recording is active the state is checkpointed every k steps
- * (pm_set_checkpoint).
+ * (pm_set_checkpoint).  Without a recording and with timing off, a call is
+ * only kernel launches on the bound stream (no allocation, no memset, no
+ * synchronisation), so it can be captured into a HIP graph and replayed.
  * Errors: PM_ESTATE, PM_EINVAL, PM_EDEVICE, PM_ENOMEM (checkpoint). */
 int pm_step(int nsteps);
 
