@@ -54,9 +54,9 @@ struct WinArgs {
     const void* coef;  // values of the accumulation type
 };
 
-// Target degrees per pass of the forward sweeps (for a storage precision and
-// row length nx) and of the transposed ones (pm_grad).
-int win_depth(int prec, int nx);
+// Target degrees per pass of the forward sweeps (for a storage precision,
+// row length nx and moment order N) and of the transposed ones (pm_grad).
+int win_depth(int prec, int nx, int N);
 int adj_depth(int prec);
 
 // Anisotropic scattering: gl = device array of g_0 .. g_N (g_0 = 1), or

@@ -15,18 +15,25 @@
 
 #include "kernels.h"
 
-// Target degrees per pass: registers (hence resident waves) against
-// re-reading the source degree that adjacent passes share.  Measured on
-// P39 64^3: FP64 K = 3 with whole-row waves held to 124 VGPRs (4
-// waves/SIMD: 176 GDoF/s; K = 2 at 96 VGPRs and 5 waves: 172), FP32 K = 2
-// where waves hold whole rows (62 VGPRs, 7 waves/SIMD: 312 vs 298 at K = 3)
-// and K = 3 otherwise (P39 160^3: 306 vs 291 at K = 2), BF16 K = 3.  The
-// transposed sweeps run at K = 2 (PM_ADJ_K64, PM_WIN_K32).
+// Target degrees per pass: registers (hence resident waves) and balanced
+// passes against re-reading the source degree that adjacent passes share.
+// Measured (GDoF-updates/s, FP64 / FP32):
+//   N <= 20: K = 2 (P7 at 64^3-160^3: +16% / up to +19%; P19: +8% / +5%);
+//   larger N: FP64 K = 3 (P39 64^3 whole-row waves held to 4 waves/SIMD:
+//   176 vs 172 at K = 2; 160^3: +5%), FP32 K = 2 where waves hold whole
+//   rows (7 waves/SIMD: 312 vs 298) and K = 3 otherwise (160^3: 306 vs 291);
+//   BF16 K = 3.  The transposed sweeps run at K = 2.
 #ifndef PM_WIN_K64
 #define PM_WIN_K64 3
 #endif
 #ifndef PM_ADJ_K64
 #define PM_ADJ_K64 2
+#endif
+#ifndef PM_WIN_KLOW
+#define PM_WIN_KLOW 2   // FP64 and FP32 at N <= PM_N_LOW
+#endif
+#ifndef PM_N_LOW
+#define PM_N_LOW 20
 #endif
 #ifndef PM_WIN_K32
 #define PM_WIN_K32 2
@@ -768,10 +775,15 @@ k_sweep_win(T* __restrict__ pool, StateOffs so, double* __restrict__ gp,
     }
 }
 
-int win_depth(int prec, int nx) {
+static_assert(PM_WIN_K64 >= 2 && PM_WIN_K64 <= 3 && PM_WIN_K32 >= 2 && PM_WIN_K32 <= 3 &&
+                  PM_WIN_K32R >= 2 && PM_WIN_K32R <= 3 && PM_WIN_KLOW >= 2 && PM_WIN_KLOW <= 3,
+              "FP64 and FP32 sweeps are instantiated for depths 2 and 3");
+
+int win_depth(int prec, int nx, int N) {
+    if (prec == kBF16) return PM_WIN_K16;
+    if (N <= PM_N_LOW) return PM_WIN_KLOW;
     if (prec == kF64) return PM_WIN_K64;
-    if (prec == kF32) return nx == 64 ? PM_WIN_K32 : PM_WIN_K32R;  // one cell per lane
-    return PM_WIN_K16;
+    return nx == 64 ? PM_WIN_K32 : PM_WIN_K32R;  // FP32: one cell per lane
 }
 int adj_depth(int prec) { return prec == kF64 ? PM_ADJ_K64 : prec == kF32 ? PM_WIN_K32 : PM_WIN_K16; }
 
@@ -781,9 +793,6 @@ int adj_depth(int prec) { return prec == kF64 ? PM_ADJ_K64 : prec == kF32 ? PM_W
 // Workgroups of 256 / CPL threads keep the LDS decay tables at 22.5 KB;
 // 512- and 1024-thread groups (up to 16 row segments stacked in z) were not
 // faster in FP64 and slower in FP32.
-#ifndef PM_CPL64
-#define PM_CPL64 1
-#endif
 #ifndef PM_CPL16
 #define PM_CPL16 2
 #endif
@@ -829,18 +838,19 @@ static void launch_fwd(void* pool, StateOffs so, const double* tab, int rowbase,
 
 hipError_t launch_sweep_win(int prec, void* pool, StateOffs so, const double* tab, int rowbase,
                             Aniso an, WinArgs a, GridDesc g, hipStream_t st) {
-    if (a.K != win_depth(prec, g.nx)) return hipErrorInvalidValue;
+    if (a.K != win_depth(prec, g.nx, a.N)) return hipErrorInvalidValue;
     // several cells per lane need whole lane groups within every row
+    // FP64 and FP32 sweeps come in depths 2 and 3
     if (prec == kF64) {
-        if (PM_CPL64 > 1 && g.nx % PM_CPL64 == 0)
-            launch_fwd<double, PM_WIN_K64, PM_CPL64>(pool, so, tab, rowbase, an, a, g, st);
+        if (a.K == 2)
+            launch_fwd<double, 2, 1>(pool, so, tab, rowbase, an, a, g, st);
         else
-            launch_fwd<double, PM_WIN_K64, 1>(pool, so, tab, rowbase, an, a, g, st);
+            launch_fwd<double, 3, 1>(pool, so, tab, rowbase, an, a, g, st);
     } else if (prec == kF32) {
-        if (a.K == PM_WIN_K32)
-            launch_fwd<float, PM_WIN_K32, 1>(pool, so, tab, rowbase, an, a, g, st);
+        if (a.K == 2)
+            launch_fwd<float, 2, 1>(pool, so, tab, rowbase, an, a, g, st);
         else
-            launch_fwd<float, PM_WIN_K32R, 1>(pool, so, tab, rowbase, an, a, g, st);
+            launch_fwd<float, 3, 1>(pool, so, tab, rowbase, an, a, g, st);
     } else {
         if (PM_CPL16 > 1 && g.nx % PM_CPL16 == 0)
             launch_fwd<bf16s, PM_WIN_K16, PM_CPL16>(pool, so, tab, rowbase, an, a, g, st);
