@@ -315,3 +315,19 @@ def test_long_rows_linear_tiles(shape):
         e = relerr(gpu_run(N, shape, h, dt, sa, ss, q, u, 3, prec=prec), ref)
         say("long rows %s prec %d err %.2e" % (shape, prec, e))
         assert e <= tol, prec
+
+
+@pytest.mark.parametrize("N", [20, 21])
+@pytest.mark.parametrize("shape", [(2, 2, 64), (2, 3, 48)])
+def test_window_depth_threshold(N, shape):
+    """The sweeps take two target degrees per pass up to N = 20 and the
+    per-type depth above (three for FP64; FP32 three where x neighbours are
+    loaded): both sides of the switch, whole-row and loaded rows, FP64 and
+    FP32 against the oracle."""
+    sa, ss, q, u = rand_problem(N, shape, 70 + N)
+    h, dt = 0.1, 0.04
+    ref = st.run(st.Setup(N, shape, h, dt, sa, ss, q), u, 2)
+    for prec, tol in ((pm.PM_FP64, 1e-13), (pm.PM_FP32, FP32_TOL)):
+        e = relerr(gpu_run(N, shape, h, dt, sa, ss, q, u, 2, prec=prec), ref)
+        say("depth threshold N=%d %s prec %d err %.2e" % (N, shape, prec, e))
+        assert e <= tol, prec
