@@ -259,9 +259,8 @@ def main():
                     help="size of the calibration copy (0: skip)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only (the step is measured on one "
-              "MI355X; multi-GPU sharding is a design note, not an implementation).",
-              file=sys.stderr)
+        print("bench.py: one GPU only: the step runs and is measured on a single MI355X; "
+              "sharding the box across GPUs is not implemented.", file=sys.stderr)
         sys.exit(2)
 
     import paper_2004_02833_amd as pm
