@@ -158,6 +158,23 @@ def copy_ceiling(gib):
     return {"bytes_per_copy": 2 * n * 4, "gbs": round(2 * n * 4 / sec / 1e9, 1)}
 
 
+def degree_band_errors(w, state, ref_state):
+    """Normwise error per band of degrees l (l = 0, then four equal bands),
+    each relative to the largest reference value in its band."""
+    idx = state_moments(w)
+    deg = np.floor(np.sqrt(np.array(idx))).astype(int)
+    edges = [0, 1] + [1 + (w.N * k + 3) // 4 for k in range(1, 4)] + [w.N + 1]
+    out = {}
+    for lo, hi in zip(edges[:-1], edges[1:]):
+        sel = [j for j in range(len(idx)) if lo <= deg[j] < hi]
+        if not sel:
+            continue
+        num = max(float(np.abs(state[j] - ref_state[j]).max()) for j in sel)
+        den = max(float(np.abs(ref_state[j]).max()) for j in sel)
+        out["l=%d" % lo if hi == lo + 1 else "l=%d-%d" % (lo, hi - 1)] = num / den if den > 0 else None
+    return out
+
+
 def state_moments(w):
     """Moments read back for the comparison between forms: all of them on
     grids up to ~1e9 values, an evenly spaced sample of 100 beyond (host
@@ -194,32 +211,44 @@ def roofline(N, ncell, esz, times):
 
 def adjoint_timing(pm):
     """Forward (recorded) and reverse pass of the gradient workload: P7,
-    64^3, 200 steps, checkpoints every 20 steps, FP64."""
+    64^3, 200 steps, checkpoints every 20 steps, in FP64 and in FP32 storage;
+    the FP32 gradients are compared with the FP64 ones (normwise)."""
     import torch
     import workloads
     w = workloads.p7_adjoint()
     dev = torch.device("cuda", 0)
-    pm.pm_set_precision(pm.PM_FP64)
-    pm.pm_bind_stream(torch.cuda.current_stream(dev).cuda_stream)
-    pm.pm_init(w.N, w.n, w.n, w.n, w.h, w.dt, w.sigma_a, w.sigma_s, w.q)
-    try:
-        for i in range(w.V):
-            pm.pm_write(i, w.moment(i))
-        pm.pm_set_checkpoint(w.checkpoint)
-        pm.pm_sync()
-        t0 = time.perf_counter()
-        pm.pm_step(w.nsteps)
-        pm.pm_sync()
-        t1 = time.perf_counter()
-        g = np.ones(w.shape)
-        pm.pm_grad(g)
-        t2 = time.perf_counter()
-    finally:
-        pm.pm_finalize()
-        pm.pm_bind_stream(0)
-    return {"workload": "%s: P%d, %d^3, %d steps, checkpoint every %d, fp64"
-                        % (w.name, w.N, w.n, w.nsteps, w.checkpoint),
-            "forward_ms": round((t1 - t0) * 1e3, 2), "grad_ms": round((t2 - t1) * 1e3, 2)}
+    target = np.zeros(w.shape)
+    out = {"workload": "%s: P%d, %d^3, %d steps, checkpoint every %d"
+                       % (w.name, w.N, w.n, w.nsteps, w.checkpoint)}
+    grads = {}
+    for name, prec in (("fp64", pm.PM_FP64), ("fp32", pm.PM_FP32)):
+        pm.pm_set_precision(prec)
+        pm.pm_bind_stream(torch.cuda.current_stream(dev).cuda_stream)
+        pm.pm_init(w.N, w.n, w.n, w.n, w.h, w.dt, w.sigma_a, w.sigma_s, w.q)
+        try:
+            for i in range(w.V):
+                pm.pm_write(i, w.moment(i))
+            pm.pm_set_checkpoint(w.checkpoint)
+            pm.pm_sync()
+            t0 = time.perf_counter()
+            pm.pm_step(w.nsteps)
+            pm.pm_sync()
+            t1 = time.perf_counter()
+            u0 = pm.pm_read(0)
+            t2 = time.perf_counter()
+            grads[name] = pm.pm_grad(u0 - target)
+            t3 = time.perf_counter()
+        finally:
+            pm.pm_finalize()
+            pm.pm_bind_stream(0)
+        out[name] = {"forward_ms": round((t1 - t0) * 1e3, 2), "grad_ms": round((t3 - t2) * 1e3, 2)}
+    for k, name in enumerate(("dsigma_a", "dsigma_s")):
+        ref = grads["fp64"][k]
+        out["fp32"]["rel_err_%s_vs_fp64" % name] = float(np.abs(grads["fp32"][k] - ref).max()
+                                                        / np.abs(ref).max())
+    # the FP64 numbers at the top level, as before
+    out["forward_ms"], out["grad_ms"] = out["fp64"]["forward_ms"], out["fp64"]["grad_ms"]
+    return out
 
 
 def cpu_baseline(w, steps, threads=0):
@@ -300,6 +329,7 @@ def main():
                 max(float(np.abs(a - b).max()) for a, b in zip(state, ref_state))
                 / max(float(np.abs(b).max()) for b in ref_state))
             res["moments_compared"] = len(state)
+            res["rel_err_by_degree"] = degree_band_errors(w, state, ref_state)
         results[form] = res
         del state
     del ref_state

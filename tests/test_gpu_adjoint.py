@@ -72,3 +72,23 @@ def test_grad_p7_reduced_vs_c_oracle():
     assert abs(L - L2) <= 1e-12 * L
     assert relerr(ga2, ga) <= 1e-11
     assert relerr(gs2, gs) <= 1e-11
+
+
+@pytest.mark.parametrize("N,shape,nsteps,ck", [(3, (4, 5, 64), 5, 2), (7, (3, 4, 6), 4, 4)])
+def test_grad_fp32_storage(N, shape, nsteps, ck):
+    """FP32 storage: the gradient against the FP64 oracle adjoint (reported;
+    the FP32 state rounding bounds it loosely)."""
+    say("case adjoint fp32", N, shape, nsteps, ck)
+    rng = np.random.default_rng(N * 11 + nsteps)
+    sa = rng.uniform(0, 0.5, shape)
+    ss = rng.uniform(0, 1, shape)
+    q = rng.uniform(0, 1, shape)
+    u = rng.normal(size=((N + 1) ** 2,) + shape)
+    tgt = rng.normal(size=shape)
+    h, dt = 0.2, 0.07
+    L, ga, gs, _ = adj.loss_and_grad(st.Setup(N, shape, h, dt, sa, ss, q), u, nsteps, tgt)
+    L2, ga2, gs2 = gpu_grad(N, shape, h, dt, sa, ss, q, u, nsteps, ck, tgt, prec=pm.PM_FP32)
+    ea, es = relerr(ga2, ga), relerr(gs2, gs)
+    say("  fp32 grad err %.2e %.2e" % (ea, es))
+    assert abs(L - L2) <= 1e-5 * L
+    assert ea <= 1e-4 and es <= 1e-4
