@@ -102,3 +102,32 @@ def test_reactor_500_cubed_p19():
     ztop = int(np.nonzero(q[:, y0, x0] > 0)[0].max())
     corners = [(n // 2 - 4, y0 - 4, x0 - 4), (ztop - 3, y0 - 2, x0 - 5)]
     check(w, (pm.PM_FP32, pm.PM_BF16), 2, corners)
+
+
+def test_p7_lattice_full_length_fp32_vs_fp64():
+    """The P7 lattice configuration over its full 400 steps, where the oracle
+    would need the whole domain: FP32 storage against the FP64 run (all 64
+    moments, normwise, within the FP32 target), both finite; after one step
+    from the zero state sum u_0 is exactly dt * sum q (no absorption on the
+    source block)."""
+    w = workloads.p7_lattice()
+    n = w.n
+    out = {}
+    for prec in (pm.PM_FP64, pm.PM_FP32):
+        say("  p7_lattice %s 128^3, %d steps" % (NAME[prec], w.nsteps))
+        pm.pm_set_precision(prec)
+        pm.pm_init(w.N, n, n, n, w.h, w.dt, w.sigma_a, w.sigma_s, w.q)
+        try:
+            pm.pm_step(1)
+            total = pm.pm_total()
+            tol = 1e-12 if prec == pm.PM_FP64 else 1e-6
+            assert abs(total - w.dt * w.q.sum()) <= tol * w.dt * w.q.sum()
+            pm.pm_step(w.nsteps - 1)
+            mx, bad = pm.pm_check()
+            assert bad == 0 and mx > 0
+            out[prec] = np.stack([pm.pm_read(i) for i in range(w.V)])
+        finally:
+            pm.pm_finalize()
+    e = relerr(out[pm.PM_FP32], out[pm.PM_FP64])
+    say("  p7_lattice 400 steps: fp32 vs fp64 %.2e" % e)
+    assert e <= 1e-5
