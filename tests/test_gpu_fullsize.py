@@ -131,3 +131,64 @@ def test_p7_lattice_full_length_fp32_vs_fp64():
     e = relerr(out[pm.PM_FP32], out[pm.PM_FP64])
     say("  p7_lattice 400 steps: fp32 vs fp64 %.2e" % e)
     assert e <= 1e-5
+
+
+def _full_length_forms(w, precs, moments):
+    """Run w over its full step count in each storage form; return the
+    normwise error of every other form against the first, over `moments`,
+    computed on the device."""
+    dev = torch.device("cuda", 0)
+    n = w.n
+    ref, err = None, {}
+    buf = torch.empty(w.shape, dtype=torch.float64, device=dev)
+    for prec in precs:
+        say("  %s %s %d^3, %d steps" % (w.name, NAME[prec], n, w.nsteps))
+        pm.pm_set_precision(prec)
+        pm.pm_bind_stream(torch.cuda.current_stream(dev).cuda_stream)
+        pm.pm_init(w.N, n, n, n, w.h, w.dt, w.sigma_a, w.sigma_s, w.q)
+        try:
+            for i in range(w.V):
+                plane = w.moment_device(i, dev)
+                pm.pm_write_dev(i, plane.data_ptr())
+                del plane
+            pm.pm_step(w.nsteps)
+            mx, bad = pm.pm_check()
+            assert bad == 0 and mx > 0
+            if ref is None:
+                ref = {}
+                for i in moments:
+                    pm.pm_read_dev(i, buf.data_ptr())
+                    ref[i] = buf.clone()
+                pm.pm_sync()
+            else:
+                num = den = 0.0
+                for i in moments:
+                    pm.pm_read_dev(i, buf.data_ptr())
+                    num = max(num, float((buf - ref[i]).abs().max()))
+                    den = max(den, float(ref[i].abs().max()))
+                err[prec] = num / den
+        finally:
+            pm.pm_finalize()
+            pm.pm_bind_stream(0)
+    return err
+
+
+def test_p39_smooth_full_length_forms():
+    """P39 at 64^3 over its 100 steps: FP32 and BF16 storage against the FP64
+    run over all 1600 moments (FP32 within its target; BF16 reported)."""
+    w = workloads.p39_smooth()
+    err = _full_length_forms(w, (pm.PM_FP64, pm.PM_FP32, pm.PM_BF16), range(w.V))
+    say("  p39_smooth 100 steps: fp32 %.2e bf16 %.2e" % (err[pm.PM_FP32], err[pm.PM_BF16]))
+    assert err[pm.PM_FP32] <= 1e-5
+    assert err[pm.PM_BF16] <= 1e-1
+
+
+def test_p39_large_full_length_forms():
+    """P39 at 160^3 over its 50 steps: FP32 and BF16 storage against the FP64
+    run on 100 evenly spaced moments."""
+    w = workloads.p39_large()
+    moments = sorted(set(np.linspace(0, w.V - 1, 100).astype(int).tolist()))
+    err = _full_length_forms(w, (pm.PM_FP64, pm.PM_FP32, pm.PM_BF16), moments)
+    say("  p39_large 50 steps: fp32 %.2e bf16 %.2e" % (err[pm.PM_FP32], err[pm.PM_BF16]))
+    assert err[pm.PM_FP32] <= 1e-5
+    assert err[pm.PM_BF16] <= 1e-1
