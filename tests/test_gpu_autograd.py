@@ -27,7 +27,7 @@ def loss_grad_autograd(sa, ss, q, u0, N, h, dt, nsteps, ck, target, prec=0):
     tg = torch.tensor(target, device=dev)
     L = 0.5 * ((u0T - tg) ** 2).sum()
     L.backward()
-    out = (float(L), tsa.grad.cpu().numpy(), tss.grad.cpu().numpy())
+    out = (float(L.detach()), tsa.grad.cpu().numpy(), tss.grad.cpu().numpy())
     pm.pm_finalize()
     return out
 
