@@ -162,7 +162,9 @@ long long plane_stride(long long ncell) {
 // one coefficient slot; the count is checked.
 int build_window_tables(int K, pm::WinArgs (&win)[2], void** mem) {
     const pm::Layout& L = C.L;
-    const int N = C.N, V = C.V, MU1 = N + 2;
+    // columns mu = 0..N+1 and one empty column N+2: a sweep requests the next
+    // column's sources unconditionally
+    const int N = C.N, V = C.V, MU1 = N + 3;
     std::unordered_map<long long, double> flux;
     long long nnz_par[2] = {0, 0};
     for (const pm::FluxEntry& e : pm::flux_entries(N)) {

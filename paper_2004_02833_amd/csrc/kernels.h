@@ -28,7 +28,7 @@ struct GridDesc {
 };
 
 // Window sweep (see kernels.hip).  A sweep of one parity is split into
-// passes of K target degrees; pass p, source column mu (0 <= mu <= N + 1)
+// passes of K target degrees; pass p, source column mu (0 <= mu <= N + 2)
 // is described by host-built streams, in the order the kernel consumes them:
 //   src[((p * MU1 + mu) * (K + 1) + b) * 2 + ty] = {slot or -1, parity bits}
 //       (slots count from the first plane of the dual parity; targets from
@@ -43,7 +43,8 @@ struct GridDesc {
 //           2: z to column mu (same m)        3: x to column mu+1   4: y to column mu+1
 //       value K = s * M_d[i, j] / dx (s = +1 if the source is unstaggered in
 //       d, else -1), zero where the target does not exist.
-// with MU1 = N + 2 and L0 = parity + 2 K p.
+// with MU1 = N + 3 (source columns 0..N+1 and an empty column N+2, so the
+// next column can always be requested) and L0 = parity + 2 K p.
 struct WinArgs {
     int N;
     int parity;   // parity (l mod 2) of the target moments

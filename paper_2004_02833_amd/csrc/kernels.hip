@@ -524,7 +524,7 @@ k_sweep_win(T* __restrict__ pool, StateOffs so, double* __restrict__ gp,
     constexpr int kRowQ = ANI ? 8 * K : 10;
     __shared__ double tl[kRowQ + 1][TPB * CPL];
     const int tid = threadIdx.x;
-    const int MU1 = N + 2;
+    const int MU1 = N + 3;  // source columns 0..N+1 and an empty column N+2
     const int L0 = parity + 2 * K * pass;
     if (ANI) {
 #pragma unroll
@@ -638,7 +638,15 @@ k_sweep_win(T* __restrict__ pool, StateOffs so, double* __restrict__ gp,
                     dy[k] = vy[k] - vc[k];
                     dz[k] = vz[k] - vc[k];
                 }
-                if (mu <= mumax) win_fetch<T, CPL, XROT>(R[b][ty], sv, sdn[b * 2 + ty], nb, ps);
+                // Empty asm taking the differences: they are formed here and
+                // not sunk into the branch below, past the loads of the next
+                // column, where the old source values would stay live beside
+                // the new ones (more registers, copies at the loop edge).
+#pragma unroll
+                for (int k = 0; k < CPL; ++k) asm volatile("" ::"v"(dx[k]), "v"(dy[k]), "v"(dz[k]));
+                // the stream ends with an empty column, so the next one can
+                // always be requested
+                win_fetch<T, CPL, XROT>(R[b][ty], sv, sdn[b * 2 + ty], nb, ps);
                 if (e.x < 0) continue;
 #pragma unroll
                 for (int side = 0; side < 2; ++side) {
@@ -666,16 +674,16 @@ k_sweep_win(T* __restrict__ pool, StateOffs so, double* __restrict__ gp,
                 for (int t = 0; t < K; ++t)
 #pragma unroll
                     for (int ty = 0; ty < 2; ++ty) tcur[t][ty] = tpf[t][ty];
-                if (mu <= mumax) {
+                {
                     const int2* tdn = td + mu * K * 2;
 #pragma unroll
                     for (int t = 0; t < K; ++t)
 #pragma unroll
                         for (int ty = 0; ty < 2; ++ty) {
                             const int2 dn = tdn[t * 2 + ty];
-                            if (dn.x >= 0)
-                                tpf[t][ty] = __builtin_nontemporal_load(
-                                    (const V*)(tin + (long long)dn.x * ps + nb.c0));
+                            tpf[t][ty] = dn.x >= 0 ? __builtin_nontemporal_load(
+                                                         (const V*)(tin + (long long)dn.x * ps + nb.c0))
+                                                   : V{};
                         }
                 }
             }
