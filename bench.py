@@ -2,9 +2,12 @@
 
 Workload: the P39 smooth-medium problem, 64^3 periodic cells, 1600 moments
 (p39_smooth in workloads.py).  A step is one full Strang step (odd half step,
-even full step, odd half step: three sweep launches) over the whole grid, with
-the state resident in HBM.  The metric is GDoF-updates/s = cells * moments *
-steps / seconds / 1e9 (the paper's MLCUP/s times 1e-3).
+even full step, odd half step) over the whole grid, with the state resident in
+HBM.  `value` runs them with the two odd half steps of consecutive steps
+merged into one full odd step (2n+1 sweep launches for n steps); the literal
+three-launch schedule is timed too ("three_sweep").  The metric is
+GDoF-updates/s = cells * moments * steps / seconds / 1e9 (the paper's MLCUP/s
+times 1e-3).
 
 Prints ONE JSON line.  `value` is the FP64 path; the FP32 path is timed on
 the same workload and reported in "fp32" together with its error against the
@@ -199,6 +202,19 @@ def ceilings(ncell):
             "unit": "GB/s"}
 
 
+def step_model(N, esz, value):
+    """Algorithmic bytes per DoF-update of one steady-state step: the literal
+    schedule (two odd half-step sweeps and one even sweep) and the merged one
+    (one odd and one even sweep), with the fraction of the HBM peak that the
+    measured rate implies for each.  The kernel-level figure is `roofline`."""
+    V, ve, vo = parity_counts(N)
+    three = ((4 * ve + 5 * vo) * esz + 2 * TABLE_BYTES[1] + TABLE_BYTES[0]) / V
+    merged = ((3 * ve + 3 * vo) * esz + TABLE_BYTES[1] + TABLE_BYTES[0]) / V
+    return {"bytes_per_dof_three_sweep": round(three, 3), "bytes_per_dof_merged": round(merged, 3),
+            "frac_at_three_sweep_bytes": round(value * three / HBM_PEAK_GBS, 4),
+            "frac_at_merged_bytes": round(value * merged / HBM_PEAK_GBS, 4)}
+
+
 def roofline(N, ncell, esz, times):
     n_odd, ms_odd = times["odd"]
     per_launch = ms_odd / max(n_odd, 1) / 1e3
@@ -330,6 +346,7 @@ def main():
                 / max(float(np.abs(b).max()) for b in ref_state))
             res["moments_compared"] = len(state)
             res["rel_err_by_degree"] = degree_band_errors(w, state, ref_state)
+        res["step_model"] = step_model(w.N, esz, res["value"])
         results[form] = res
         del state
     del ref_state
@@ -369,6 +386,7 @@ def main():
                                % (w.name, w.N, V, w.n, w.n),
                    "cells": ncell, "moments": V, "seed": w.seed},
         "roofline": head["roofline"],
+        "step_model": head["step_model"],
         "forms": {f: r for f, r in results.items() if f != forms[0]},
         "adjoint": adjoint,
         "cpu_baseline": cpu,

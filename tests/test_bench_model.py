@@ -1,0 +1,37 @@
+"""The byte models of bench.py (no GPU): the per-launch sweep bytes, the two
+per-step models, and the moment counts they use, checked against each other
+and against the P39 counts (V = 1600, 780 even and 820 odd moments)."""
+import bench
+
+
+def test_parity_counts_p39():
+    assert bench.parity_counts(39) == (1600, 780, 820)
+    assert bench.parity_counts(3) == (16, 6, 10)
+    assert bench.parity_counts(7) == (64, 28, 36)
+
+
+def test_odd_sweep_bytes_p39_64():
+    # dual (even) planes read once, odd planes read and written, 8 table values
+    ncell = 64 ** 3
+    assert bench.sweep_bytes(39, ncell, 8, 1) == ncell * ((780 + 2 * 820) * 8 + 64)
+    assert bench.sweep_bytes(39, ncell, 8, 1) == 5091885056
+    assert bench.sweep_bytes(39, ncell, 4, 0) == ncell * ((820 + 2 * 780) * 4 + 88)
+
+
+def test_step_models_are_sums_of_sweeps():
+    for N in (3, 7, 39):
+        V = bench.parity_counts(N)[0]
+        for esz in (8, 4, 2):
+            odd = bench.sweep_bytes(N, 1, esz, 1)
+            even = bench.sweep_bytes(N, 1, esz, 0)
+            m = bench.step_model(N, esz, 100.0)
+            assert abs(m["bytes_per_dof_three_sweep"] - (2 * odd + even) / V) < 1e-3
+            assert abs(m["bytes_per_dof_merged"] - (odd + even) / V) < 1e-3
+
+
+def test_step_model_fractions():
+    m = bench.step_model(39, 8, 183.867)
+    assert abs(m["bytes_per_dof_three_sweep"] - 36.235) < 1e-3
+    assert abs(m["frac_at_three_sweep_bytes"] - 183.867 * 36.235 / 8000) < 1e-3
+    m32 = bench.step_model(39, 4, 345.3)
+    assert abs(m32["bytes_per_dof_three_sweep"] - 18.185) < 1e-3
