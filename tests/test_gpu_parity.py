@@ -290,8 +290,10 @@ def test_rectangular_cells(N, shape, h):
 def test_whole_row_waves(shape):
     """Rows of 64 cells (FP64, FP32) or 128 cells (BF16, two per lane) are
     held by one wave, whose x neighbours come by lane rotation, periodic
-    wrap included; other row lengths load them.  All three forms against
-    the oracle, P7 (every staggering combination of sources and targets)."""
+    wrap included; other row lengths load them.  With nz = 3 and 5 the last
+    tile of four z-stacked waves has waves past the grid, which still take
+    part in every column barrier.  All three forms against the oracle, P7
+    (every staggering combination of sources and targets)."""
     N = 7
     sa, ss, q, u = rand_problem(N, shape, 51)
     h, dt = 0.1, 0.04
