@@ -477,7 +477,8 @@ constexpr int min_waves() {
 // degree, grid) pair of the pass are formed once per cell from
 // c_l = mean sigma_a + (1 - g_l) mean sigma_s with the per-degree moments gl
 // and the substep length tau, and kept in LDS.  XROT: whole-row waves (see
-// win_fetch).
+// win_fetch), in every mode: the push phase is the same forward-shaped
+// stencil for the transposed sweeps.
 template <class T, int K, int TPB, int CPL, int MODE, bool ANI, bool XROT>
 __global__ void __launch_bounds__(TPB, (min_waves<T, MODE, ANI, XROT>()))
 k_sweep_win(T* __restrict__ pool, StateOffs so, double* __restrict__ gp,
@@ -488,7 +489,6 @@ k_sweep_win(T* __restrict__ pool, StateOffs so, double* __restrict__ gp,
             TileMap tm, GridDesc g) {
     static_assert(MODE == kFwd || CPL == 1, "transposed sweeps use one cell per lane");
     static_assert(!(ANI && MODE == kAdjDual), "the dual side reads no decay factors");
-    static_assert(!XROT || MODE == kFwd, "row rotation only in the forward sweep");
     // every plane is addressed from one base: sources (the dual parity),
     // targets read and written (equal offsets for an update in place)
     const T* sv = pool + so.src;
@@ -831,8 +831,8 @@ static void launch_win_t(T* pool, StateOffs so, double* gp, const double* tab, i
     const int per_xcd = (int)((ntile + kXcds - 1) / kXcds);
     const unsigned nwg = (unsigned)((long long)kXcds * per_xcd * a.npass);
     // one whole row per wave: x neighbours by lane rotation
-    if (MODE == kFwd && sw == g.nx && g.nx == 64 * CPL)
-        hipLaunchKernelGGL((k_sweep_win<T, K, TPB, CPL, MODE, ANI, MODE == kFwd>), dim3(nwg),
+    if (sw == g.nx && g.nx == 64 * CPL)
+        hipLaunchKernelGGL((k_sweep_win<T, K, TPB, CPL, MODE, ANI, true>), dim3(nwg),
                            dim3(TPB), 0, st, pool, so, gp, tab, a.src, a.tgt, (const A*)a.coef,
                            an.gl, an.tau, rowbase, a.N, a.parity, a.npass, per_xcd, ntile, tm, g);
     else
