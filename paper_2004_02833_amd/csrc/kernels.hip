@@ -625,7 +625,9 @@ k_sweep_win(T* __restrict__ pool, StateOffs so, double* __restrict__ gp,
                         first = R[b][ty].c[0];
                         last = R[b][ty].c[CPL - 1];
                     }
-                    xv = (A)s1_val<T>(back ? rot<false>(last) : rot<true>(first));
+                    // both rotations and a select rather than a branch
+                    const S1 from_prev = rot<false>(last), from_next = rot<true>(first);
+                    xv = (A)s1_val<T>(back ? from_prev : from_next);
                 } else {
                     xv = (A)s1_val<T>(R[b][ty].xe);
                 }
@@ -693,9 +695,12 @@ k_sweep_win(T* __restrict__ pool, StateOffs so, double* __restrict__ gp,
                 for (int ty = 0; ty < 2; ++ty) {
                     const int2 d = tdc[t * 2 + ty];
                     if (d.x < 0) continue;
+                    // only the degree-0 cos slot can be moment 0 (a test the
+                    // compiler drops for every other slot)
+                    const bool m0 = t == 0 && ty == 0 && d.y == kTabMom0;
                     // moment 0 (row code kTabMom0) is grid G111, degree 0, under ANI
                     const int ra = ANI ? 2 * (4 * t + ((d.y >> 1) & 3))
-                                       : d.y == kTabMom0 ? 8 : 2 * ((d.y >> 1) & 3);
+                                       : m0 ? 8 : 2 * ((d.y >> 1) & 3);
                     T* ut = tout + (long long)d.x * ps + nb.c0;
                     A old[CPL];
                     if constexpr (MODE == kFwd)
@@ -706,7 +711,7 @@ k_sweep_win(T* __restrict__ pool, StateOffs so, double* __restrict__ gp,
                     if constexpr (MODE == kFwd) {
 #pragma unroll
                         for (int k = 0; k < CPL; ++k) {
-                            const double q = d.y == kTabMom0 ? tl[kRowQ][tid * CPL + k] : 0.0;
+                            const double q = m0 ? tl[kRowQ][tid * CPL + k] : 0.0;
                             nv[k] = tl[ra][tid * CPL + k] * (double)old[k] +
                                     tl[ra + 1][tid * CPL + k] * (q - (double)S[0][t][ty][k]);
                         }
@@ -716,7 +721,7 @@ k_sweep_win(T* __restrict__ pool, StateOffs so, double* __restrict__ gp,
                         // old[0] is lam_i; the old u_i comes from the source state
                         const double lam = (double)old[0];
                         const double uo = (double)ld(pool + so.aux + (long long)d.x * ps + nb.c0);
-                        const double q = d.y == kTabMom0 ? tl[kRowQ][tid] : 0.0;
+                        const double q = m0 ? tl[kRowQ][tid] : 0.0;
                         const double r = q - (double)S[0][t][ty][0];
                         if constexpr (ANI) {
                             // dL/dc = lam (u d alpha/dc + r d beta/dc), with c
@@ -738,7 +743,7 @@ k_sweep_win(T* __restrict__ pool, StateOffs so, double* __restrict__ gp,
                                     gb[f4] += ws * gx;
                                 }
                         } else {
-                            const int set = d.y == kTabMom0 ? 4 : ((d.y >> 1) & 3);
+                            const int set = m0 ? 4 : ((d.y >> 1) & 3);
 #pragma unroll
                             for (int s5 = 0; s5 < 5; ++s5)
                                 if (s5 == set) {
