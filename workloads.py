@@ -74,6 +74,14 @@ class Workload:
         return torch.from_numpy(self.moment(i)).to(device)
 
 
+def _device_zeros(n):
+    """Zero initial moments made on the device (no host plane to copy)."""
+    def fn(i, device):
+        import torch
+        return torch.zeros((n, n, n), dtype=torch.float64, device=device)
+    return fn
+
+
 def _coords(n):
     c = (np.arange(n) + 0.5) / n
     z, y, x = np.meshgrid(c, c, c, indexing="ij")
@@ -134,7 +142,8 @@ def p7_lattice(seed=1, n=128, N=7, nsteps=400):
     def moment(i):
         return np.zeros((n, n, n))
 
-    return Workload("p7_lattice", N, n, nsteps, sa, ss, q, moment, seed)
+    return Workload("p7_lattice", N, n, nsteps, sa, ss, q, moment, seed,
+                    extra={"device_moment_fn": _device_zeros(n)})
 
 
 def smooth_field(n, rng, modes=8, kmax=4):
@@ -250,7 +259,8 @@ def reactor(seed=4, n=500, N=19, nsteps=20, name="reactor"):
         return np.zeros((n, n, n))
 
     w = Workload(name, N, n, nsteps, sa, ss, q, moment, seed,
-                 extra={"rod": rod, "pitch": pitch, "shell": shell, "offset": off})
+                 extra={"rod": rod, "pitch": pitch, "shell": shell, "offset": off,
+                        "device_moment_fn": _device_zeros(n)})
     return w
 
 
