@@ -64,18 +64,24 @@ __device__ __forceinline__ float ld(const bf16s* p) {
     return __uint_as_float((uint32_t)p->b << 16);
 }
 
-// Round-to-nearest-even conversions from the float64 update.
+// Two float values rounded to nearest even into bfloat16, the first in the
+// low half: one packed hardware conversion (v_cvt_pk_bf16_f32).  For every
+// non-NaN input it gives the bits of rounding the float's bit pattern by
+// hand (add 0x7fff plus the kept lowest bit, keep the high half), checked
+// over all 2^32 inputs; a NaN stays a NaN.
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t bf_pack2(float a, float b) {
+    const f32x2_t v = {a, b};
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2_t));
+}
+
+// Round-to-nearest-even conversions from the float64 update (bfloat16: via
+// float, as the FP32 form stores it, then to bfloat16).
 __device__ __forceinline__ void st(double* p, double v) { *p = v; }
 __device__ __forceinline__ void st(float* p, double v) { *p = (float)v; }
 __device__ __forceinline__ void st(bf16s* p, double v) {
-    float f = (float)v;
-    uint32_t x = __float_as_uint(f);
-    uint16_t r;
-    if ((x & 0x7fffffffu) > 0x7f800000u)
-        r = (uint16_t)((x >> 16) | 0x40u);  // quiet NaN
-    else
-        r = (uint16_t)((x + 0x7fffu + ((x >> 16) & 1u)) >> 16);
-    p->b = r;
+    p->b = (uint16_t)(bf_pack2((float)v, 0.0f) & 0xffffu);
 }
 
 // Streaming (non-temporal) access for values that are read once and written
@@ -313,10 +319,10 @@ __device__ __forceinline__ typename Pack<T, CPL>::V pack(const double (&v)[CPL])
         if constexpr (CPL == 1) {
             r = (uint16_t)bf_bits(v[0]);
         } else if constexpr (CPL == 2) {
-            r = bf_bits(v[0]) | (bf_bits(v[1]) << 16);
+            r = bf_pack2((float)v[0], (float)v[1]);
         } else {
-            r.x = bf_bits(v[0]) | (bf_bits(v[1]) << 16);
-            r.y = bf_bits(v[2]) | (bf_bits(v[3]) << 16);
+            r.x = bf_pack2((float)v[0], (float)v[1]);
+            r.y = bf_pack2((float)v[2], (float)v[3]);
         }
     } else if constexpr (CPL == 1) {
         r = (T)v[0];
