@@ -353,12 +353,13 @@ struct LaneNbr {
 
 // Wavefront rotations by one lane (DPP wave_rol:1 / wave_ror:1): lane i
 // receives the value of lane i + 1 (next) or i - 1 (prev), modulo 64.
-// Every lane of the wave must be active.
+// Every lane of the wave must be active; every lane then reads a valid lane,
+// so no old value has to be supplied (no register to clear first).
 __device__ __forceinline__ uint32_t rot_next(uint32_t v) {
-    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x134, 0xf, 0xf, false);
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x134, 0xf, 0xf, false);
 }
 __device__ __forceinline__ uint32_t rot_prev(uint32_t v) {
-    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x13C, 0xf, 0xf, false);
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x13C, 0xf, 0xf, false);
 }
 template <bool NEXT> __device__ __forceinline__ double rot(double v) {
     const uint32_t lo = (uint32_t)__double2loint(v), hi = (uint32_t)__double2hiint(v);
@@ -521,6 +522,15 @@ k_sweep_win(T* __restrict__ pool, StateOffs so, double* __restrict__ gp,
         nb.ym = n0.off[3];
         nb.zp = n0.off[4];
         nb.zm = n0.off[5];
+    }
+    if constexpr (XROT) {
+        // a wave is one row (or, past the grid, one cell): its y and z
+        // neighbour rows are the same for every lane, so the offsets and the
+        // choice between them live in scalar registers
+        nb.yp = __builtin_amdgcn_readfirstlane(nb.yp);
+        nb.ym = __builtin_amdgcn_readfirstlane(nb.ym);
+        nb.zp = __builtin_amdgcn_readfirstlane(nb.zp);
+        nb.zm = __builtin_amdgcn_readfirstlane(nb.zm);
     }
     const long long ps = g.pstride;
     // decay factors for the lane's cells, kept in LDS instead of registers:
