@@ -20,14 +20,17 @@
 // Measured (GDoF-updates/s, FP64 / FP32):
 //   N <= 20: K = 2 (P7 at 64^3-160^3: +16% / up to +19%; P19: +8% / +5%);
 //   larger N: FP64 K = 3 (P39 64^3 whole-row waves held to 4 waves/SIMD:
-//   176 vs 172 at K = 2; 160^3: +5%), FP32 K = 2 where waves hold whole
-//   rows (7 waves/SIMD: 312 vs 298) and K = 3 otherwise (160^3: 306 vs 291);
-//   BF16 K = 3.  The transposed sweeps run at K = 2.
+//   180 vs 178 at K = 2; 160^3: +5%), FP32 K = 2 where waves hold whole
+//   rows (7 waves/SIMD; K = 3 at 7 waves within noise) and K = 3 otherwise
+//   (160^3: 306 vs 291); BF16 K = 3.  The transposed sweeps run at K = 2.
 #ifndef PM_WIN_K64
 #define PM_WIN_K64 3
 #endif
 #ifndef PM_ADJ_K64
 #define PM_ADJ_K64 2
+#endif
+#ifndef PM_ADJ_K32
+#define PM_ADJ_K32 2
 #endif
 #ifndef PM_WIN_KLOW
 #define PM_WIN_KLOW 2   // FP64 and FP32 at N <= PM_N_LOW
@@ -810,7 +813,8 @@ k_sweep_win(T* __restrict__ pool, StateOffs so, double* __restrict__ gp,
     }
 }
 
-static_assert(PM_WIN_K64 >= 2 && PM_WIN_K64 <= 3 && PM_WIN_K32 >= 2 && PM_WIN_K32 <= 3 &&
+static_assert(PM_ADJ_K64 >= 2 && PM_ADJ_K64 <= 3 && PM_ADJ_K32 >= 2 && PM_ADJ_K32 <= 3 &&
+                  PM_WIN_K64 >= 2 && PM_WIN_K64 <= 3 && PM_WIN_K32 >= 2 && PM_WIN_K32 <= 3 &&
                   PM_WIN_K32R >= 2 && PM_WIN_K32R <= 3 && PM_WIN_KLOW >= 2 && PM_WIN_KLOW <= 3,
               "FP64 and FP32 sweeps are instantiated for depths 2 and 3");
 
@@ -820,7 +824,7 @@ int win_depth(int prec, int nx, int N) {
     if (prec == kF64) return PM_WIN_K64;
     return nx == 64 ? PM_WIN_K32 : PM_WIN_K32R;  // FP32: one cell per lane
 }
-int adj_depth(int prec) { return prec == kF64 ? PM_ADJ_K64 : prec == kF32 ? PM_WIN_K32 : PM_WIN_K16; }
+int adj_depth(int prec) { return prec == kF64 ? PM_ADJ_K64 : prec == kF32 ? PM_ADJ_K32 : PM_WIN_K16; }
 
 
 // Launch shape, measured on P39 64^3.  Cells per lane: 1 for FP64 and FP32
@@ -913,7 +917,7 @@ hipError_t launch_adj_win(int prec, int side, void* pool, StateOffs so, double* 
     if (prec == kF64)
         launch_adj_t<double, PM_ADJ_K64>(side, pool, so, gp, tab, rowbase, an, a, g, st);
     else
-        launch_adj_t<float, PM_WIN_K32>(side, pool, so, gp, tab, rowbase, an, a, g, st);
+        launch_adj_t<float, PM_ADJ_K32>(side, pool, so, gp, tab, rowbase, an, a, g, st);
     return hipGetLastError();
 }
 
