@@ -50,12 +50,14 @@ extern "C" {
 
 #define PM_FP64 0 /* state, accumulation and update in float64                 */
 #define PM_FP32 1 /* float32 state and accumulation; update in float64, rounded */
-#define PM_BF16 2 /* bfloat16 state (storage probe); float32 accumulation       */
+#define PM_BF16 2 /* bfloat16 state (storage probe); float32 accumulation and update */
 
 #define PM_N_MAX 63
 
 /* Storage precision used by the next pm_init (default PM_FP64).  The decay
- * factors exp(-c tau) and tau E(-c tau) are always kept in float64.
+ * factors exp(-c tau) and tau E(-c tau) are always computed and kept in
+ * float64; FP64 and FP32 apply them in float64, the BF16 storage probe
+ * rounds them to float32 for its float32 update.
  * Returns PM_EINVAL for an unknown value. */
 int pm_set_precision(int precision);
 

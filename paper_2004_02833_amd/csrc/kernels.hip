@@ -336,6 +336,22 @@ __device__ __forceinline__ typename Pack<T, CPL>::V pack(const double (&v)[CPL])
     return r;
 }
 
+// bfloat16 storage from float values (the FP32 update of BF16 storage)
+template <class T, int CPL>
+__device__ __forceinline__ typename Pack<T, CPL>::V pack_f(const float (&v)[CPL]) {
+    static_assert(std::is_same<T, bf16s>::value, "float update only for bfloat16 storage");
+    typename Pack<T, CPL>::V r;
+    if constexpr (CPL == 1) {
+        r = (uint16_t)(bf_pack2(v[0], 0.0f) & 0xffffu);
+    } else if constexpr (CPL == 2) {
+        r = bf_pack2(v[0], v[1]);
+    } else {
+        r.x = bf_pack2(v[0], v[1]);
+        r.y = bf_pack2(v[2], v[3]);
+    }
+    return r;
+}
+
 template <class T> __device__ __forceinline__ float s1_val(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
 template <class T> __device__ __forceinline__ T s1_val(T x) { return x; }
 
@@ -541,7 +557,12 @@ k_sweep_win(T* __restrict__ pool, StateOffs so, double* __restrict__ gp,
     // ANI: target degree t and grid f in rows 2 (4 t + f), 2 (4 t + f) + 1,
     // q in row 8 K
     constexpr int kRowQ = ANI ? 8 * K : 10;
-    __shared__ double tl[kRowQ + 1][TPB * CPL];
+    // BF16 storage is a storage form: its update runs in FP32, with the
+    // float64 factors rounded to float once when staged (half the LDS, and
+    // no FP64 arithmetic per cell; its own rounding, 2^-9, is far larger)
+    constexpr bool kF32Update = std::is_same<T, bf16s>::value;
+    using TabT = typename std::conditional<kF32Update, float, double>::type;
+    __shared__ TabT tl[kRowQ + 1][TPB * CPL];
     const int tid = threadIdx.x;
     const int MU1 = N + 3;  // source columns 0..N+1 and an empty column N+2
     const int L0 = parity + 2 * K * pass;
@@ -726,6 +747,17 @@ k_sweep_win(T* __restrict__ pool, StateOffs so, double* __restrict__ gp,
                         unpack<T, CPL, A>(tcur[t][ty], old);
                     else
                         unpack<T, CPL, A>(__builtin_nontemporal_load((const V*)(tin + (long long)d.x * ps + nb.c0)), old);
+                    if constexpr (MODE == kFwd && kF32Update) {
+                        float nf[CPL];
+#pragma unroll
+                        for (int k = 0; k < CPL; ++k) {
+                            const float q = m0 ? (float)tl[kRowQ][tid * CPL + k] : 0.0f;
+                            nf[k] = (float)tl[ra][tid * CPL + k] * (float)old[k] +
+                                    (float)tl[ra + 1][tid * CPL + k] * (q - (float)S[0][t][ty][k]);
+                        }
+                        if (live) __builtin_nontemporal_store(pack_f<T, CPL>(nf), (V*)ut);
+                        continue;
+                    }
                     double nv[CPL];
                     if constexpr (MODE == kFwd) {
 #pragma unroll
