@@ -861,7 +861,8 @@ int adj_depth(int prec) { return prec == kF64 ? PM_ADJ_K64 : prec == kF32 ? PM_A
 
 // Launch shape, measured on P39 64^3.  Cells per lane: 1 for FP64 and FP32
 // (2 was slower: more registers per wave), 2 for BF16 (4-byte accesses; +7%).
-// Workgroups of 256 / CPL threads keep the LDS decay tables at 22.5 KB;
+// Workgroups of 256 / CPL threads keep the LDS decay tables at 22.5 KB
+// (11 KB for BF16, which stages them as float);
 // 512- and 1024-thread groups (up to 16 row segments stacked in z) were not
 // faster in FP64 and slower in FP32.
 #ifndef PM_CPL16
