@@ -35,3 +35,24 @@ def test_step_model_fractions():
     assert abs(m["frac_at_three_sweep_bytes"] - 183.867 * 36.235 / 8000) < 1e-3
     m32 = bench.step_model(39, 4, 345.3)
     assert abs(m32["bytes_per_dof_three_sweep"] - 18.185) < 1e-3
+
+
+def test_source_hash_ignores_comments_not_code(tmp_path, monkeypatch):
+    """Recorded traffic counters stay valid across comment and whitespace
+    edits of the device sources and are invalidated by code edits."""
+    import os
+    import shutil
+    src = os.path.join(bench.ROOT, "paper_2004_02833_amd", "csrc")
+    dst = tmp_path / "paper_2004_02833_amd" / "csrc"
+    shutil.copytree(src, dst)
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    h0 = bench.kernel_source_hash()
+    k = dst / "kernels.hip"
+    text = k.read_text()
+    k.write_text(text.replace("namespace pm {", "namespace pm {  // a comment\n\n", 1))
+    assert bench.kernel_source_hash() == h0
+    k.write_text(text.replace("namespace pm {", "namespace pm {\nconstexpr int kUnused = 1;", 1))
+    assert bench.kernel_source_hash() != h0
+    k.write_text(text)
+    (dst / "probe.hip").write_text("// measurement only\nint changed;\n")
+    assert bench.kernel_source_hash() == h0
