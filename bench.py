@@ -54,7 +54,7 @@ def kernel_source_hash():
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_2004_02833_amd", "csrc")
     for name in sorted(os.listdir(d)):
-        if name.endswith((".hip", ".h")) and name != "probe.hip":
+        if name.endswith((".hip", ".h")):
             text = open(os.path.join(d, name)).read()
             text = re.sub(r"//[^\n]*", "", text)
             h.update(re.sub(r"\s+", "", text).encode())
@@ -86,7 +86,12 @@ def sync():
         pass
 
 
-def run_gpu(pm, w, prec, steps, warmup, keep_state=False):
+def run_gpu(pm, w, prec, steps, warmup, reps, keep_state=False):
+    """Warmup, then exactly `steps` timed steps (the headline block, no
+    per-sweep events), then `reps` more blocks of `steps` steps with HIP
+    events around every sweep launch on the library's stream (the roofline:
+    median over the blocks of the mean launch time), then one block with the
+    literal three-sweep schedule."""
     import torch
     n = w.n
     dev = torch.device("cuda", 0)
@@ -103,14 +108,17 @@ def run_gpu(pm, w, prec, steps, warmup, keep_state=False):
         pm.pm_step(warmup)
         pm.pm_sync()
         sync()
-        pm.pm_timing(1)
         t0 = time.perf_counter()
         pm.pm_step(steps)
         pm.pm_sync()
         sync()
         t1 = time.perf_counter()
-        times = pm.pm_sweep_times()
-        pm.pm_timing(0)
+        blocks = []
+        for _ in range(reps):
+            pm.pm_timing(1)
+            pm.pm_step(steps)
+            blocks.append(pm.pm_sweep_times())
+            pm.pm_timing(0)
         # the same steps with every step as its three substeps
         pm.pm_set_merge(0)
         t2 = time.perf_counter()
@@ -119,7 +127,6 @@ def run_gpu(pm, w, prec, steps, warmup, keep_state=False):
         sync()
         t3 = time.perf_counter()
         pm.pm_set_merge(1)
-        times["three_sweep_s"] = t3 - t2
         state = None
         if keep_state:
             # sampled moments, and on very large grids every k-th cell of them
@@ -131,7 +138,7 @@ def run_gpu(pm, w, prec, steps, warmup, keep_state=False):
                 state.append(buf.reshape(-1)[::stride].cpu().numpy())
             del buf
         maxabs, nonfinite = pm.pm_check()
-        return t1 - t0, times, state, (maxabs, nonfinite)
+        return t1 - t0, blocks, t3 - t2, state, (maxabs, nonfinite)
     finally:
         pm.pm_finalize()
         pm.pm_bind_stream(0)
@@ -191,7 +198,11 @@ def ceilings(ncell):
     """Measured bandwidth ceilings (libpm_probe.so): flat read, flat copy and
     a pure-memory kernel with the sweeps' access pattern, in GB/s."""
     import ctypes
-    lib = ctypes.CDLL(os.path.join(ROOT, "paper_2004_02833_amd", "libpm_probe.so"))
+    path = os.path.join(ROOT, "bench_probe", "libpm_probe.so")
+    if not os.path.exists(path):
+        from bench_probe import build as probe_build
+        probe_build.build()
+    lib = ctypes.CDLL(path)
     lib.pmp_ceilings.argtypes = [ctypes.c_longlong, ctypes.c_longlong, ctypes.POINTER(ctypes.c_double)]
     out = (ctypes.c_double * 4)()
     rc = lib.pmp_ceilings(4 << 30, (ncell // 256) * 256, out)
@@ -202,27 +213,33 @@ def ceilings(ncell):
             "unit": "GB/s"}
 
 
-def step_model(N, esz, value):
-    """Algorithmic bytes per DoF-update of one steady-state step: the literal
-    schedule (two odd half-step sweeps and one even sweep) and the merged one
-    (one odd and one even sweep), with the fraction of the HBM peak that the
-    measured rate implies for each.  The kernel-level figure is `roofline`."""
+def step_bytes(N, esz):
+    """Algorithmic bytes per DoF-update of one steady-state step for the
+    literal schedule (two odd half-step sweeps and one even sweep) and the
+    merged one that pm_step runs (one odd and one even sweep).  Bytes only:
+    the bandwidth figure is the kernel's roofline."""
     V, ve, vo = parity_counts(N)
     three = ((4 * ve + 5 * vo) * esz + 2 * TABLE_BYTES[1] + TABLE_BYTES[0]) / V
     merged = ((3 * ve + 3 * vo) * esz + TABLE_BYTES[1] + TABLE_BYTES[0]) / V
-    return {"bytes_per_dof_three_sweep": round(three, 3), "bytes_per_dof_merged": round(merged, 3),
-            "frac_at_three_sweep_bytes": round(value * three / HBM_PEAK_GBS, 4),
-            "frac_at_merged_bytes": round(value * merged / HBM_PEAK_GBS, 4)}
+    return {"bytes_per_dof_three_sweep": round(three, 3), "bytes_per_dof_merged": round(merged, 3)}
 
 
-def roofline(N, ncell, esz, times):
-    n_odd, ms_odd = times["odd"]
-    per_launch = ms_odd / max(n_odd, 1) / 1e3
+def roofline(N, ncell, esz, blocks):
+    """The dominant kernel (the odd sweep): algorithmic bytes per launch over
+    its launch time, the median over the timed blocks of each block's mean."""
+    per = sorted(b["odd"][1] / max(b["odd"][0], 1) for b in blocks)
+    per_even = sorted(b["even"][1] / max(b["even"][0], 1) for b in blocks)
+    med = per[len(per) // 2] / 1e3
     byts = sweep_bytes(N, ncell, esz, 1)
-    achieved = byts / per_launch / 1e9
+    achieved = byts / med / 1e9
+    ebytes = sweep_bytes(N, ncell, esz, 0)
+    emed = per_even[len(per_even) // 2] / 1e3
     return {"kernel": "sweep_odd", "bound": "hbm", "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "bytes_per_launch": byts, "ms_per_launch": round(per_launch * 1e3, 4)}
+            "bytes_per_launch": byts, "ms_per_launch": round(med * 1e3, 4),
+            "ms_per_launch_blocks": [round(x, 4) for x in per], "launches_per_block": blocks[0]["odd"][0],
+            "even_sweep": {"ms_per_launch": round(emed * 1e3, 4), "bytes_per_launch": ebytes,
+                           "frac": round(ebytes / emed / 1e9 / HBM_PEAK_GBS, 4)}}
 
 
 def adjoint_timing(pm):
@@ -283,12 +300,53 @@ def cpu_baseline(w, steps, threads=0):
                       % (steps, w.nsteps, w.name, w.N, w.n, dt)}
 
 
+def time_forms(pm, w, forms, args, say):
+    """Time each storage form of workload w; the first form is the
+    reference for the error of the others (sampled moments, normwise and per
+    band of degrees)."""
+    PREC = {"fp64": (pm.PM_FP64, 8, "f64"), "fp32": (pm.PM_FP32, 4, "f32"),
+            "bf16": (pm.PM_BF16, 2, "bf16")}
+    ncell, V = w.n ** 3, w.V
+    results = {}
+    ref_state = None
+    for k, form in enumerate(forms):
+        prec, esz, dname = PREC[form]
+        say("bench: %s P%d %d^3, %s, %d warmup + %d steps, %d roofline blocks"
+            % (w.name, w.N, w.n, form, args.warmup, args.steps, args.reps))
+        keep = len(forms) > 1
+        t, blocks, t3, state, chk = run_gpu(pm, w, prec, args.steps, args.warmup, args.reps,
+                                            keep_state=keep)
+        r = roofline(w.N, ncell, esz, blocks)
+        r["traffic"] = measured_traffic("sweep_odd", w.name, dname)
+        res = {"value": round(ncell * V * args.steps / t / 1e9, 3),
+               "ms_per_step": round(t / args.steps * 1e3, 4),
+               "three_sweep": {"value": round(ncell * V * args.steps / t3 / 1e9, 3),
+                               "ms_per_step": round(t3 / args.steps * 1e3, 4)},
+               "dtype": dname, "roofline": r, "step_bytes": step_bytes(w.N, esz),
+               "state_check": {"max_abs": chk[0], "nonfinite": chk[1]}}
+        if k == 0:
+            ref_state = state
+        elif state is not None and ref_state is not None:
+            res["rel_err_vs_%s_gpu" % forms[0]] = (
+                max(float(np.abs(a - b).max()) for a, b in zip(state, ref_state))
+                / max(float(np.abs(b).max()) for b in ref_state))
+            res["moments_compared"] = len(state)
+            res["rel_err_by_degree"] = degree_band_errors(w, state, ref_state)
+        results[form] = res
+        del state
+    return results
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--reps", type=int, default=5,
+                    help="timed blocks of --steps steps for the roofline (median)")
     ap.add_argument("--workload", default="p39_smooth")
+    ap.add_argument("--large", default="p39_large",
+                    help="second workload timed in the same line ('none' to skip)")
     ap.add_argument("--cpu-steps", type=int, default=8)
     ap.add_argument("--cpu-steps-1thread", type=int, default=1,
                     help="steps of the one-thread oracle sample (0: skip)")
@@ -307,6 +365,8 @@ def main():
         print("bench.py: one GPU only: the step runs and is measured on a single MI355X; "
               "sharding the box across GPUs is not implemented.", file=sys.stderr)
         sys.exit(2)
+    if args.reps < 1:
+        ap.error("--reps must be >= 1")
 
     import paper_2004_02833_amd as pm
     import workloads
@@ -323,34 +383,17 @@ def main():
         forms.remove("fp32")
     if args.bf16 and "bf16" not in forms:
         forms.append("bf16")
-    PREC = {"fp64": (pm.PM_FP64, 8, "f64"), "fp32": (pm.PM_FP32, 4, "f32"), "bf16": (pm.PM_BF16, 2, "bf16")}
-    results = {}
-    ref_state = None
-    for k, form in enumerate(forms):
-        prec, esz, dname = PREC[form]
-        say("bench: %s P%d %d^3, %s, %d warmup + %d steps" % (w.name, w.N, w.n, form, args.warmup, args.steps))
-        keep = len(forms) > 1
-        t, times, state, chk = run_gpu(pm, w, prec, args.steps, args.warmup, keep_state=keep)
-        r = roofline(w.N, ncell, esz, times)
-        r["traffic"] = measured_traffic("sweep_odd", w.name, dname)
-        res = {"value": round(ncell * V * args.steps / t / 1e9, 3), "ms_per_step": round(t / args.steps * 1e3, 4),
-               "three_sweep": {"value": round(ncell * V * args.steps / times["three_sweep_s"] / 1e9, 3),
-                               "ms_per_step": round(times["three_sweep_s"] / args.steps * 1e3, 4)},
-               "dtype": dname, "roofline": r, "state_check": {"max_abs": chk[0], "nonfinite": chk[1]},
-               "sweep_ms": {"odd": times["odd"], "even": times["even"]}}
-        if k == 0:
-            ref_state = state
-        elif state is not None and ref_state is not None:
-            res["rel_err_vs_%s_gpu" % forms[0]] = (
-                max(float(np.abs(a - b).max()) for a, b in zip(state, ref_state))
-                / max(float(np.abs(b).max()) for b in ref_state))
-            res["moments_compared"] = len(state)
-            res["rel_err_by_degree"] = degree_band_errors(w, state, ref_state)
-        res["step_model"] = step_model(w.N, esz, res["value"])
-        results[form] = res
-        del state
-    del ref_state
+    results = time_forms(pm, w, forms, args, say)
     head = results[forms[0]]
+
+    large = None
+    if args.large and args.large != "none" and args.large != args.workload:
+        wl = workloads.RECIPES[args.large]()
+        lres = time_forms(pm, wl, forms, args, say)
+        large = {"workload": "%s: P%d (%d moments), %d^3 periodic cells, dx=1/%d, dt=dx/2"
+                             % (wl.name, wl.N, wl.V, wl.n, wl.n),
+                 "cells": wl.n ** 3, "moments": wl.V, "forms": lres}
+        del wl
 
     adjoint = None
     if not args.no_adjoint:
@@ -386,8 +429,9 @@ def main():
                                % (w.name, w.N, V, w.n, w.n),
                    "cells": ncell, "moments": V, "seed": w.seed},
         "roofline": head["roofline"],
-        "step_model": head["step_model"],
+        "step_bytes": head["step_bytes"],
         "forms": {f: r for f, r in results.items() if f != forms[0]},
+        "large": large,
         "adjoint": adjoint,
         "cpu_baseline": cpu,
         "cpu_baseline_1thread": cpu1,
@@ -396,7 +440,6 @@ def main():
         "copy_ceiling": copy,
         "ceilings": ceil,
         "state_check": head["state_check"],
-        "sweep_ms": head["sweep_ms"],
     }
     print(json.dumps(out), flush=True)
 

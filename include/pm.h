@@ -152,6 +152,21 @@ int pm_set_checkpoint(int k);
  * PM_EDEVICE. */
 int pm_grad(const double* dL_du0, double* dsigma_a, double* dsigma_s);
 
+/* Same with device pointers: dL_du0 holds nx*ny*nz float64 values on the
+ * device; dsigma_a and dsigma_s (either may be NULL) receive nx*ny*nz
+ * float64 values on the device.  The caller keeps ownership of all three.
+ * The work is queued on the bound stream; the call returns after it has
+ * finished (the pass frees its temporaries).  Errors as pm_grad. */
+int pm_grad_dev(const void* dL_du0, void* dsigma_a, void* dsigma_s);
+
+/* Identifier of the recorded forward that pm_grad would differentiate: it
+ * changes whenever a recording starts or stops (pm_set_checkpoint), is
+ * dropped (pm_write, pm_write_dev, pm_init, pm_init_cells, pm_finalize) or
+ * is extended (pm_step while recording).  A caller that stores it after its
+ * forward can tell whether pm_grad still refers to that forward.  Never
+ * fails. */
+long long pm_recording_id(void);
+
 /* Float64 sum of moment 0 over all cells (total intensity; conserved when
  * sigma_a = 0 and q = 0).  Synchronises. */
 int pm_total(double* sum_u0);

@@ -1,14 +1,19 @@
 """torch.autograd.Function around the C ABI: forward runs the P_N steps,
-backward runs the library's transposed steps (pm_grad).
+backward runs the library's transposed steps (pm_grad_dev).
 
 Torch supplies tensors and the stream only; all arithmetic runs in libpm.
 The library holds one global context, so a forward must be followed by its
-backward before the next forward.
+backward before the next forward: the forward stores the library's
+recording id, and a backward whose recording has been replaced or extended
+since then raises instead of returning another run's gradients.
 """
-import numpy as np
 import torch
 
 from . import binding as pm
+
+
+class StaleRecordingError(RuntimeError):
+    """The library context no longer holds the forward this backward belongs to."""
 
 
 class PmRun(torch.autograd.Function):
@@ -37,14 +42,24 @@ class PmRun(torch.autograd.Function):
         out = torch.empty(shape, dtype=torch.float64, device=dev)
         pm.pm_read_dev(0, out.data_ptr())
         ctx.shape = shape
-        ctx.dev = sigma_a.device
+        ctx.dev = dev
+        ctx.in_dev = sigma_a.device
+        ctx.recording = pm.pm_recording_id()
         return out
 
     @staticmethod
     def backward(ctx, grad_u0):
-        g = np.ascontiguousarray(grad_u0.detach().to("cpu", torch.float64).numpy())
-        dsa, dss = pm.pm_grad(g)
-        return (torch.from_numpy(dsa).to(ctx.dev), torch.from_numpy(dss).to(ctx.dev), None)
+        if pm.pm_recording_id() != ctx.recording:
+            raise StaleRecordingError(
+                "libpm's recorded forward changed since this forward ran (another forward, "
+                "pm_init, pm_write, pm_step or pm_finalize came in between); run each "
+                "backward before the next forward")
+        g = grad_u0.detach().to(ctx.dev, torch.float64).contiguous()
+        dsa = torch.empty(ctx.shape, dtype=torch.float64, device=ctx.dev)
+        dss = torch.empty(ctx.shape, dtype=torch.float64, device=ctx.dev)
+        pm.pm_bind_stream(torch.cuda.current_stream(ctx.dev).cuda_stream)
+        pm.pm_grad_dev(g.data_ptr(), dsa.data_ptr(), dss.data_ptr())
+        return dsa.to(ctx.in_dev), dss.to(ctx.in_dev), None
 
 
 def run_u0(sigma_a, sigma_s, spec):

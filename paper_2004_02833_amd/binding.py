@@ -19,7 +19,8 @@ PM_N_MAX = 63
 
 EXPORTED = ("pm_set_precision", "pm_set_scattering", "pm_init", "pm_init_cells", "pm_write", "pm_write_dev", "pm_step", "pm_set_merge",
             "pm_read",
-            "pm_read_dev", "pm_set_checkpoint", "pm_grad", "pm_total", "pm_check",
+            "pm_read_dev", "pm_set_checkpoint", "pm_grad", "pm_grad_dev", "pm_recording_id",
+            "pm_total", "pm_check",
             "pm_bind_stream", "pm_sync", "pm_cfl_warning", "pm_timing", "pm_sweep_times",
             "pm_finalize", "pm_last_error", "pm_flux_nnz", "pm_flux_entries", "pm_moment_grid",
             "pm_moment_slot", "pm_device_bytes")
@@ -60,6 +61,8 @@ def lib():
             "pm_read_dev": ([i32, vp], i32),
             "pm_set_checkpoint": ([i32], i32),
             "pm_grad": ([P(f64), P(f64), P(f64)], i32),
+            "pm_grad_dev": ([vp, vp, vp], i32),
+            "pm_recording_id": ([], i64),
             "pm_total": ([P(f64)], i32),
             "pm_check": ([P(f64), P(i64)], i32),
             "pm_bind_stream": ([vp], i32),
@@ -205,6 +208,17 @@ def pm_grad(dL_du0):
     dss = np.empty(shape)
     _check(lib().pm_grad(_dptr(g), _dptr(dsa), _dptr(dss)))
     return dsa, dss
+
+
+def pm_grad_dev(dL_du0_ptr, dsigma_a_ptr, dsigma_s_ptr):
+    """Device-pointer form of pm_grad (integers, e.g. tensor.data_ptr();
+    0 for an output that is not wanted)."""
+    vp = lambda p: ctypes.c_void_p(int(p)) if p else None
+    return _check(lib().pm_grad_dev(vp(dL_du0_ptr), vp(dsigma_a_ptr), vp(dsigma_s_ptr)))
+
+
+def pm_recording_id():
+    return int(lib().pm_recording_id())
 
 
 def pm_total():

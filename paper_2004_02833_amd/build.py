@@ -9,7 +9,6 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpm.so")
-PROBE_LIB = os.path.join(HERE, "libpm_probe.so")
 ARCH = "gfx950"
 
 # Packed FP32 instructions are disabled for all device code.
@@ -37,14 +36,6 @@ def build(verbose=False):
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
     os.replace(tmp, LIB)
-    # bandwidth probes whose ceilings bench.py reports beside the roofline (measurement only)
-    tmp = PROBE_LIB + ".tmp"
-    cmd = ["hipcc"] + COMMON + ["-x", "hip"] + DEVFLAGS + ["-shared", "-o", tmp,
-                                                          os.path.join(CSRC, "probe.hip")]
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    subprocess.check_call(cmd)
-    os.replace(tmp, PROBE_LIB)
     return LIB
 
 

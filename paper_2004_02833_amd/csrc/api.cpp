@@ -108,10 +108,15 @@ void dfree(void* p) {
     if (p) (void)hipFree(p);
 }
 
+// Identifies the recorded forward: changes whenever the recording starts,
+// stops, is dropped or is extended by pm_step (pm_recording_id).
+long long g_rec_id = 1;
+
 void drop_recording() {
     for (void* p : C.ckpts) dfree(p);
     C.ckpts.clear();
     C.rec_steps = 0;
+    ++g_rec_id;
 }
 
 void drop_events() {
@@ -527,6 +532,7 @@ int pm_step(int nsteps) {
         done += chunk;
         if (C.ck > 0) C.rec_steps += chunk;
     }
+    if (C.ck > 0 && nsteps > 0) ++g_rec_id;
     return PM_OK;
 }
 
@@ -578,7 +584,13 @@ int pm_set_checkpoint(int k) {
 // j of a segment with state (E_j, O_j): O'_j = S^o half step, E'_j = S^e,
 // O''_j = S^o again, and state j + 1 = (E'_j, O''_j).  The transposes then
 // run on (E'_j, O'_j), (E_j, O'_j) and (E_j, O_j).
-int pm_grad(const double* dL_du0, double* dsa, double* dss) {
+}  // extern "C"
+
+namespace {
+
+// Reverse pass; dL_du0, dsa and dss are host pointers (dev = false) or
+// device pointers (dev = true).
+int grad_impl(const double* dL_du0, double* dsa, double* dss, bool dev) {
     if (!C.live) return fail(PM_ESTATE, "no context: call pm_init first");
     if (C.ck <= 0) return fail(PM_ESTATE, "no gradient recording: call pm_set_checkpoint(k > 0) before pm_step");
     if (!dL_du0) return fail(PM_EINVAL, "dL_du0 is NULL");
@@ -646,8 +658,8 @@ int pm_grad(const double* dL_du0, double* dsa, double* dss) {
     auto O2 = [&](long long j) { return reg(j) + OH + EH; };
     HIPG(pm::launch_fill_zero(pool, (long long)(C.esz * (size_t)SE), s));
     HIPG(pm::launch_fill_zero(gpass, (long long)(gpb * (np0 + np1)), s));
-    HIPG(hipMemcpyAsync(C.plane64, dL_du0, sizeof(double) * n, hipMemcpyHostToDevice, s));
-    HIPG(pm::launch_from_f64(C.prec, C.plane64, C.plane(pool, C.L.slot_of[0]), n, s));
+    if (!dev) HIPG(hipMemcpyAsync(C.plane64, dL_du0, sizeof(double) * n, hipMemcpyHostToDevice, s));
+    HIPG(pm::launch_from_f64(C.prec, dev ? dL_du0 : C.plane64, C.plane(pool, C.L.slot_of[0]), n, s));
     double* gp_par[2] = {gpass, gpass + (size_t)np0 * pm::kGradRows * (size_t)n};
     C.timing = false;
     auto fwd = [&](int p, long long src, long long tin, long long tout) -> hipError_t {
@@ -690,15 +702,34 @@ int pm_grad(const double* dL_du0, double* dsa, double* dss) {
         }
     }
     HIPG(pm::launch_grad_sum(gpass, np0 + np1, grad, n, s));
-    HIPG(pm::launch_grad_final(grad, C.tab, C.sig, C.sig + n, outg, outg + n, C.g, C.dt, C.aniso, s));
-    if (dsa) HIPG(hipMemcpyAsync(dsa, outg, sizeof(double) * n, hipMemcpyDeviceToHost, s));
-    if (dss) HIPG(hipMemcpyAsync(dss, outg + n, sizeof(double) * n, hipMemcpyDeviceToHost, s));
+    if (dev) {
+        HIPG(pm::launch_grad_final(grad, C.tab, C.sig, C.sig + n, dsa, dss, C.g, C.dt, C.aniso, s));
+    } else {
+        HIPG(pm::launch_grad_final(grad, C.tab, C.sig, C.sig + n, outg, outg + n, C.g, C.dt, C.aniso, s));
+        if (dsa) HIPG(hipMemcpyAsync(dsa, outg, sizeof(double) * n, hipMemcpyDeviceToHost, s));
+        if (dss) HIPG(hipMemcpyAsync(dss, outg + n, sizeof(double) * n, hipMemcpyDeviceToHost, s));
+    }
+    // the temporaries are freed below: the queued work must be done first
     HIPG(hipStreamSynchronize(s));
     cleanup();
 #undef TRYG
 #undef HIPG
     return PM_OK;
 }
+
+}  // namespace
+
+extern "C" {
+
+int pm_grad(const double* dL_du0, double* dsa, double* dss) {
+    return grad_impl(dL_du0, dsa, dss, false);
+}
+
+int pm_grad_dev(const void* dL_du0, void* dsa, void* dss) {
+    return grad_impl((const double*)dL_du0, (double*)dsa, (double*)dss, true);
+}
+
+long long pm_recording_id(void) { return g_rec_id; }
 
 int pm_total(double* out) {
     if (!C.live) return fail(PM_ESTATE, "no context: call pm_init first");

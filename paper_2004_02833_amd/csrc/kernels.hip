@@ -434,6 +434,68 @@ struct TileMap {
     int nty, ntz;  // tiles per direction
 };
 
+// Tile order within the contiguous range of an XCD (segment tiles only).
+// PM_TILE_GZ > 0 groups the tiles in blocks of PM_TILE_GY y-tiles x
+// PM_TILE_GZ z-tiles (segments fastest, then y, then z inside a block;
+// blocks by y within a z-group), so the workgroups resident at one time
+// cover a compact (y, z) block and more of their one-sided neighbour rows
+// are rows that a resident sibling reads.  0 keeps segments fastest, then
+// y, then z over the whole grid.
+#ifndef PM_TILE_GZ
+#define PM_TILE_GZ 0
+#endif
+#ifndef PM_TILE_GY
+#define PM_TILE_GY 4
+#endif
+// Passes dispatched together: 1 = pass-major (every tile of the heaviest
+// pass first); G > 1 interleaves G adjacent passes of the same tile, so the
+// source degree two adjacent passes share is read by both at about the same
+// time.
+#ifndef PM_PASS_GROUP
+#define PM_PASS_GROUP 1
+#endif
+
+__device__ __forceinline__ long long tile_order(const TileMap& m, long long t) {
+    if (PM_TILE_GZ <= 0 || m.sw == 0) return t;
+    const long long A = (long long)m.nseg * m.nty;
+    const long long zg = t / (A * PM_TILE_GZ);
+    long long r = t - zg * A * PM_TILE_GZ;
+    const int gz = min(PM_TILE_GZ, m.ntz - (int)zg * PM_TILE_GZ);
+    const long long B = (long long)m.nseg * PM_TILE_GY * gz;
+    const long long yb = r / B;
+    r -= yb * B;
+    const int gy = min(PM_TILE_GY, m.nty - (int)yb * PM_TILE_GY);
+    const long long seg = r % m.nseg;
+    r /= m.nseg;
+    const long long ty = yb * PM_TILE_GY + r % gy;
+    const long long tz = zg * PM_TILE_GZ + r / gy;
+    return seg + m.nseg * (ty + (long long)m.nty * tz);
+}
+
+// Workgroup id -> (tile, pass); false for an id past the grid.  Workgroups
+// are dispatched round-robin over the XCDs (id mod 8); each XCD gets a
+// contiguous range of per_xcd tiles.
+__device__ __forceinline__ bool block_work(const TileMap& m, int npass, int per_xcd,
+                                           long long ntile, long long& tile, int& pass) {
+    const int xcd = blockIdx.x % kXcds;
+    const int j = blockIdx.x / kXcds;
+    int ti;
+    if (PM_PASS_GROUP <= 1) {
+        ti = j % per_xcd;
+        pass = npass - 1 - j / per_xcd;
+    } else {
+        const int q = j / (per_xcd * PM_PASS_GROUP);
+        const int r = j - q * per_xcd * PM_PASS_GROUP;
+        const int gq = min(PM_PASS_GROUP, npass - q * PM_PASS_GROUP);
+        ti = r / gq;
+        pass = npass - 1 - q * PM_PASS_GROUP - r % gq;
+    }
+    const long long t = (long long)xcd * per_xcd + ti;
+    if (pass < 0 || t >= ntile) return false;
+    tile = tile_order(m, t);
+    return true;
+}
+
 template <int TPB, int CPL>
 __device__ __forceinline__ long long tile_cell(const TileMap& m, long long tile, int tid,
                                                const GridDesc& g, bool& live) {
@@ -522,11 +584,9 @@ k_sweep_win(T* __restrict__ pool, StateOffs so, double* __restrict__ gp,
     T* tout = pool + so.tout;
     using A = typename Acc<T>::type;
     using V = typename Pack<T, CPL>::V;
-    const int xcd = blockIdx.x % kXcds;
-    const int j = blockIdx.x / kXcds;
-    const long long tile = (long long)xcd * per_xcd + (j % per_xcd);
-    const int pass = npass - 1 - j / per_xcd;
-    if (pass < 0 || tile >= ntile) return;
+    long long tile;
+    int pass;
+    if (!block_work(tm, npass, per_xcd, ntile, tile, pass)) return;
     bool live;
     const long long cl = tile_cell<TPB, CPL>(tm, tile, threadIdx.x, g, live);
     LaneNbr nb;
@@ -845,10 +905,16 @@ k_sweep_win(T* __restrict__ pool, StateOffs so, double* __restrict__ gp,
     }
 }
 
+// Deepest forward pass instantiated for FP64 and FP32 (3, or 4 for tuning).
+#ifndef PM_MAX_K
+#define PM_MAX_K 3
+#endif
 static_assert(PM_ADJ_K64 >= 2 && PM_ADJ_K64 <= 3 && PM_ADJ_K32 >= 2 && PM_ADJ_K32 <= 3 &&
-                  PM_WIN_K64 >= 2 && PM_WIN_K64 <= 3 && PM_WIN_K32 >= 2 && PM_WIN_K32 <= 3 &&
-                  PM_WIN_K32R >= 2 && PM_WIN_K32R <= 3 && PM_WIN_KLOW >= 2 && PM_WIN_KLOW <= 3,
-              "FP64 and FP32 sweeps are instantiated for depths 2 and 3");
+                  PM_WIN_K64 >= 2 && PM_WIN_K64 <= PM_MAX_K && PM_WIN_K32 >= 2 &&
+                  PM_WIN_K32 <= PM_MAX_K && PM_WIN_K32R >= 2 && PM_WIN_K32R <= PM_MAX_K &&
+                  PM_WIN_KLOW >= 2 && PM_WIN_KLOW <= PM_MAX_K && PM_MAX_K <= 4,
+              "forward FP64 and FP32 sweeps are instantiated for depths 2..PM_MAX_K, "
+              "the transposed ones for 2 and 3");
 
 int win_depth(int prec, int nx, int N) {
     if (prec == kBF16) return PM_WIN_K16;
@@ -916,11 +982,19 @@ hipError_t launch_sweep_win(int prec, void* pool, StateOffs so, const double* ta
     if (prec == kF64) {
         if (a.K == 2)
             launch_fwd<double, 2, 1>(pool, so, tab, rowbase, an, a, g, st);
+#if PM_MAX_K >= 4
+        else if (a.K == 4)
+            launch_fwd<double, 4, 1>(pool, so, tab, rowbase, an, a, g, st);
+#endif
         else
             launch_fwd<double, 3, 1>(pool, so, tab, rowbase, an, a, g, st);
     } else if (prec == kF32) {
         if (a.K == 2)
             launch_fwd<float, 2, 1>(pool, so, tab, rowbase, an, a, g, st);
+#if PM_MAX_K >= 4
+        else if (a.K == 4)
+            launch_fwd<float, 4, 1>(pool, so, tab, rowbase, an, a, g, st);
+#endif
         else
             launch_fwd<float, 3, 1>(pool, so, tab, rowbase, an, a, g, st);
     } else {

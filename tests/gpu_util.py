@@ -54,3 +54,54 @@ def window_oracle(N, shape, h, dt, sa, ss, q, u_window, corner, B, R, nsteps):
     qq = None if q is None else q[sub]
     out = c_oracle.run(N, W, h, dt, sa[sub], ss[sub], qq, u_window, nsteps)
     return out[:, R:R + B, R:R + B, R:R + B]
+
+
+def progress(msg):
+    """Progress line of a long GPU test, written when a piece of its work has
+    ended: printed, and appended to gpurun_out/gpu_tests_progress.log so that
+    a run whose output pytest captures still shows it advancing."""
+    import os
+    say(msg)
+    d = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "gpurun_out")
+    try:
+        os.makedirs(d, exist_ok=True)
+        with open(os.path.join(d, "gpu_tests_progress.log"), "a") as f:
+            f.write(msg + "\n")
+    except OSError:
+        pass
+
+
+def oracle_run_chunked(N, shape, h, dt, sa, ss, q, u0, nsteps, chunk, label):
+    """The C oracle over nsteps literal steps, run as pieces of `chunk` steps
+    (the state is the only thing carried from one step to the next), with a
+    progress line after each piece."""
+    from oracle import c_oracle
+    u = u0
+    done = 0
+    while done < nsteps:
+        k = min(chunk, nsteps - done)
+        u = c_oracle.run(N, shape, h, dt, sa, ss, q, u, k)
+        done += k
+        progress("%s: oracle %d/%d steps" % (label, done, nsteps))
+    return u
+
+
+class DegreeErrors:
+    """Normwise error over all moments and per degree l: max |x - ref| over
+    the moments of a degree divided by the largest |ref| of that degree."""
+
+    def __init__(self, N):
+        self.N = N
+        self.num = np.zeros(N + 1)
+        self.den = np.zeros(N + 1)
+
+    def add(self, i, x, ref):
+        l = int(np.floor(np.sqrt(i)))
+        self.num[l] = max(self.num[l], float(np.abs(np.asarray(x) - ref).max()))
+        self.den[l] = max(self.den[l], float(np.abs(ref).max()))
+
+    def normwise(self):
+        return float(self.num.max() / self.den.max())
+
+    def per_degree(self):
+        return self.num / np.where(self.den > 0, self.den, np.inf)

@@ -18,23 +18,30 @@ def test_odd_sweep_bytes_p39_64():
     assert bench.sweep_bytes(39, ncell, 4, 0) == ncell * ((820 + 2 * 780) * 4 + 88)
 
 
-def test_step_models_are_sums_of_sweeps():
+def test_step_bytes_are_sums_of_sweeps():
     for N in (3, 7, 39):
         V = bench.parity_counts(N)[0]
         for esz in (8, 4, 2):
             odd = bench.sweep_bytes(N, 1, esz, 1)
             even = bench.sweep_bytes(N, 1, esz, 0)
-            m = bench.step_model(N, esz, 100.0)
+            m = bench.step_bytes(N, esz)
             assert abs(m["bytes_per_dof_three_sweep"] - (2 * odd + even) / V) < 1e-3
             assert abs(m["bytes_per_dof_merged"] - (odd + even) / V) < 1e-3
+            assert set(m) == {"bytes_per_dof_three_sweep", "bytes_per_dof_merged"}
 
 
-def test_step_model_fractions():
-    m = bench.step_model(39, 8, 183.867)
-    assert abs(m["bytes_per_dof_three_sweep"] - 36.235) < 1e-3
-    assert abs(m["frac_at_three_sweep_bytes"] - 183.867 * 36.235 / 8000) < 1e-3
-    m32 = bench.step_model(39, 4, 345.3)
-    assert abs(m32["bytes_per_dof_three_sweep"] - 18.185) < 1e-3
+def test_step_bytes_p39():
+    assert abs(bench.step_bytes(39, 8)["bytes_per_dof_three_sweep"] - 36.235) < 1e-3
+    assert abs(bench.step_bytes(39, 4)["bytes_per_dof_three_sweep"] - 18.185) < 1e-3
+
+
+def test_roofline_takes_the_median_block():
+    blocks = [{"odd": (21, 21 * t), "even": (20, 20 * 0.9 * t)} for t in (1.2, 1.0, 1.1, 5.0, 1.05)]
+    r = bench.roofline(39, 64 ** 3, 8, blocks)
+    assert r["ms_per_launch"] == 1.1
+    assert abs(r["achieved"] - 5091885056 / 1.1e-3 / 1e9) < 0.1
+    assert abs(r["frac"] - r["achieved"] / 8000) < 1e-4
+    assert r["even_sweep"]["ms_per_launch"] == 0.99
 
 
 def test_source_hash_ignores_comments_not_code(tmp_path, monkeypatch):
@@ -54,5 +61,4 @@ def test_source_hash_ignores_comments_not_code(tmp_path, monkeypatch):
     k.write_text(text.replace("namespace pm {", "namespace pm {\nconstexpr int kUnused = 1;", 1))
     assert bench.kernel_source_hash() != h0
     k.write_text(text)
-    (dst / "probe.hip").write_text("// measurement only\nint changed;\n")
     assert bench.kernel_source_hash() == h0

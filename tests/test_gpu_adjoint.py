@@ -96,3 +96,51 @@ def test_grad_fp32_storage(N, shape, nsteps, ck):
     say("  fp32 grad err %.2e %.2e" % (ea, es))
     assert abs(L - L2) <= 1e-5 * L
     assert ea <= 1e-4 and es <= 1e-4
+
+
+def test_grad_p7_full_vs_c_oracle():
+    """The gradient workload at its stated size: P7, 64^3, 200 steps,
+    checkpoints every 20 steps; the target is u_0(T) of the oracle run with
+    the perturbed sigma_a.  pm_grad against the C oracle adjoint (FP64 to
+    1e-11; FP32 storage reported, bound 1e-4), and pm_grad_dev (device
+    pointers) equal to pm_grad bit for bit."""
+    import workloads
+    from gpu_util import progress
+    torch = pytest.importorskip("torch")
+    w = workloads.p7_adjoint()
+    progress("case adjoint p7 %d^3 %d steps, checkpoint %d" % (w.n, w.nsteps, w.checkpoint))
+    u0 = w.initial()
+    tgt = c_oracle.run(w.N, w.shape, w.h, w.dt, w.extra["perturbed_sigma_a"], w.sigma_s, w.q,
+                       u0, w.nsteps)[0]
+    progress("adjoint p7: oracle target done")
+    L, ga, gs = c_oracle.grad(w.N, w.shape, w.h, w.dt, w.sigma_a, w.sigma_s, w.q, u0, w.nsteps,
+                              w.checkpoint, tgt)
+    progress("adjoint p7: oracle gradient done")
+    dev = torch.device("cuda", 0)
+    errs = {}
+    for prec in (pm.PM_FP64, pm.PM_FP32):
+        gpu_init(w.N, w.shape, w.h, w.dt, w.sigma_a, w.sigma_s, w.q, prec)
+        try:
+            pm.pm_bind_stream(torch.cuda.current_stream(dev).cuda_stream)
+            for i in range(w.V):
+                pm.pm_write(i, u0[i])
+            pm.pm_set_checkpoint(w.checkpoint)
+            pm.pm_step(w.nsteps)
+            u0T = pm.pm_read(0)
+            L2 = 0.5 * float(np.sum((u0T - tgt) ** 2))
+            ga2, gs2 = pm.pm_grad(u0T - tgt)
+            g = torch.from_numpy(u0T - tgt).to(dev)
+            da = torch.empty(w.shape, dtype=torch.float64, device=dev)
+            ds = torch.empty(w.shape, dtype=torch.float64, device=dev)
+            pm.pm_grad_dev(g.data_ptr(), da.data_ptr(), ds.data_ptr())
+            assert np.array_equal(da.cpu().numpy(), ga2) and np.array_equal(ds.cpu().numpy(), gs2)
+        finally:
+            pm.pm_finalize()
+            pm.pm_bind_stream(0)
+        errs[prec] = (abs(L2 - L) / L, relerr(ga2, ga), relerr(gs2, gs))
+        progress("adjoint p7 %s: loss %.2e dsigma_a %.3e dsigma_s %.3e"
+                 % ("fp64" if prec == pm.PM_FP64 else "fp32", *errs[prec]))
+    assert errs[pm.PM_FP64][0] <= 1e-12
+    assert errs[pm.PM_FP64][1] <= 1e-11 and errs[pm.PM_FP64][2] <= 1e-11
+    assert errs[pm.PM_FP32][0] <= 1e-5
+    assert errs[pm.PM_FP32][1] <= 1e-4 and errs[pm.PM_FP32][2] <= 1e-4

@@ -93,3 +93,34 @@ def test_gradient_workload_vs_finite_differences(n, nsteps, ncell):
             say("  d/dsigma_%s %s adjoint %.10e fd %s" % (which, cell, g, ["%.10e" % v for v in vals]))
     say("worst FD rel err", worst)
     assert worst <= 1e-6
+
+
+def test_backward_after_another_forward_raises():
+    """The library keeps one recording: a backward whose forward has been
+    replaced by another forward raises instead of returning the other run's
+    gradients; the later forward's backward still works."""
+    from paper_2004_02833_amd.autograd import StaleRecordingError, run_u0
+    N, shape = 3, (4, 5, 64)
+    rng = np.random.default_rng(71)
+    q = rng.uniform(0, 1, shape)
+    u = rng.normal(size=(16,) + shape)
+    dev = torch.device("cuda", 0)
+    spec = dict(N=N, dx=0.2, dt=0.07, nsteps=5, checkpoint=2, q=q, moments=lambda i: u[i])
+    sa1 = torch.tensor(rng.uniform(0, 0.5, shape), device=dev, requires_grad=True)
+    ss1 = torch.tensor(rng.uniform(0, 1, shape), device=dev, requires_grad=True)
+    sa2 = torch.tensor(rng.uniform(0, 0.5, shape), device=dev, requires_grad=True)
+    ss2 = torch.tensor(rng.uniform(0, 1, shape), device=dev, requires_grad=True)
+    try:
+        y1 = run_u0(sa1, ss1, spec)
+        y2 = run_u0(sa2, ss2, spec)
+        with pytest.raises(StaleRecordingError):
+            y1.sum().backward()
+        y2.sum().backward()
+        assert sa2.grad is not None and torch.isfinite(sa2.grad).all()
+        # extending the recording also invalidates it
+        y3 = run_u0(sa1, ss1, spec)
+        pm.pm_step(1)
+        with pytest.raises(StaleRecordingError):
+            y3.sum().backward()
+    finally:
+        pm.pm_finalize()
