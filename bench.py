@@ -284,6 +284,72 @@ def adjoint_timing(pm):
     return out
 
 
+def halo_timing(pm, N=39, prec_name="fp32", steps=5):
+    """One GPU's share of the 160^3 P39 box split over 8 GPUs: the halo
+    faces each sweep needs (pm_halo_pack into a staging buffer, then
+    pm_halo_unpack from it; no transfer, one GPU) timed beside the sweeps of
+    that share.  Two splits: 2 x 2 x 2 (80^3 sub-boxes, x faces included:
+    one 4-byte value per 128-byte line there) and 1 x 2 x 4 (160 x 80 x 40:
+    whole x rows, only y and z faces)."""
+    import torch
+    import workloads
+    PREC = {"fp64": (pm.PM_FP64, torch.float64, 8), "fp32": (pm.PM_FP32, torch.float32, 4)}
+    prec, tdt, esz = PREC[prec_name]
+    dev = torch.device("cuda", 0)
+    out = {"moments": "P%d" % N, "dtype": prec_name, "unit": "ms"}
+    for name, (nx, ny, nz) in (("split_2x2x2", (80, 80, 80)), ("split_1x2x4", (160, 80, 40))):
+        rng = np.random.default_rng(1)
+        shape = (nz, ny, nx)
+        sa = 0.1 + 0.4 * rng.uniform(size=shape)
+        ss = 1.0 - sa
+        pm.pm_set_precision(prec)
+        pm.pm_bind_stream(torch.cuda.current_stream(dev).cuda_stream)
+        pm.pm_init(N, nx, ny, nz, 1.0 / 160, 0.5 / 160, sa, ss, None)
+        try:
+            buf = torch.empty((nz, ny, nx), dtype=torch.float64, device=dev)
+            for i in range((N + 1) ** 2):
+                buf.normal_()
+                pm.pm_write_dev(i, buf.data_ptr())
+            del buf
+            pm.pm_step(1)
+            pm.pm_timing(1)
+            pm.pm_step(steps)
+            t = pm.pm_sweep_times()
+            pm.pm_timing(0)
+            sweep_ms = (t["odd"][1] / t["odd"][0] + t["even"][1] / t["even"][0])
+            res = {"cells": nx * ny * nz, "shape_xyz": [nx, ny, nz]}
+            tot = 0.0
+            for parity in (1, 0):
+                n = pm.pm_halo_plan(N, nx, ny, nz, parity)
+                stage = torch.empty(n, dtype=tdt, device=dev)
+                ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+                pm.pm_halo_pack(parity, stage.data_ptr())       # warm
+                pm.pm_halo_unpack(parity, stage.data_ptr())
+                ev[0].record()
+                for _ in range(steps):
+                    pm.pm_halo_pack(parity, stage.data_ptr())
+                ev[1].record()
+                for _ in range(steps):
+                    pm.pm_halo_unpack(parity, stage.data_ptr())
+                ev[2].record()
+                torch.cuda.synchronize()
+                pk = ev[0].elapsed_time(ev[1]) / steps
+                un = ev[1].elapsed_time(ev[2]) / steps
+                tot += pk + un
+                res["odd_sweep" if parity else "even_sweep"] = {
+                    "halo_elements": n, "halo_mb": round(n * esz / 1e6, 2),
+                    "pack_ms": round(pk, 4), "unpack_ms": round(un, 4)}
+                del stage
+            res["sweeps_ms_per_step"] = round(sweep_ms, 4)
+            res["halo_ms_per_step"] = round(tot, 4)
+            res["halo_over_sweeps"] = round(tot / sweep_ms, 4)
+            out[name] = res
+        finally:
+            pm.pm_finalize()
+            pm.pm_bind_stream(0)
+    return out
+
+
 def cpu_baseline(w, steps, threads=0):
     """The C oracle on the host: every core (threads=0) or the given count."""
     from oracle import c_oracle
@@ -356,6 +422,7 @@ def main():
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--bf16", action="store_true", help="also time the BF16-storage probe")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the gradient timing")
+    ap.add_argument("--no-halo", action="store_true", help="skip the halo pack/unpack timing")
     ap.add_argument("--no-ceilings", action="store_true",
                     help="skip the bandwidth ceilings (libpm_probe.so)")
     ap.add_argument("--copy-gib", type=float, default=4.0,
@@ -395,6 +462,11 @@ def main():
                  "cells": wl.n ** 3, "moments": wl.V, "forms": lres}
         del wl
 
+    halo = None
+    if not args.no_halo:
+        say("bench: halo faces of an 8-GPU split (one GPU's share)")
+        halo = halo_timing(pm)
+
     adjoint = None
     if not args.no_adjoint:
         say("bench: adjoint timing")
@@ -432,6 +504,7 @@ def main():
         "step_bytes": head["step_bytes"],
         "forms": {f: r for f, r in results.items() if f != forms[0]},
         "large": large,
+        "halo": halo,
         "adjoint": adjoint,
         "cpu_baseline": cpu,
         "cpu_baseline_1thread": cpu1,

@@ -44,6 +44,12 @@ int fail(int code, const std::string& msg) {
 
 size_t elem_size(int prec) { return prec == PM_FP64 ? 8 : prec == PM_FP32 ? 4 : 2; }
 
+// Halo faces of the sweeps of one parity (see halo_plan).
+struct HaloPlan {
+    std::vector<int> slots;  // slots of the faces' moments, face after face
+    pm::HaloFaces hf{};
+};
+
 struct Ctx {
     bool live = false;
     int N = 0, V = 0, nx = 0, ny = 0, nz = 0;
@@ -57,10 +63,13 @@ struct Ctx {
     long long ve = 0;  // planes of the even parity (slots [0, ve)); odd ones follow
     void* u = nullptr;
     double* tab = nullptr;
+    float* tabf = nullptr;  // float copy for the FP32 update (float/bfloat16 storage, isotropic)
     double* sig = nullptr;  // sigma_a, sigma_s (device copies)
     bool aniso = false;     // some g_l != 0 for 1 <= l <= N
     double* gl = nullptr;   // g_0 .. g_N on the device (anisotropic scattering)
     void* win_mem = nullptr;  // window sweep streams (both parities)
+    HaloPlan halo[2];         // halo faces of the sweeps of each parity
+    int* halo_slots[2] = {nullptr, nullptr};
     void* adj_mem = nullptr;  // streams of the transposed sweeps when their depth differs
     pm::WinArgs win[2]{};     // forward sweeps
     pm::WinArgs wadj[2]{};    // transposed sweeps (pm_grad)
@@ -134,9 +143,12 @@ void release() {
     drop_events();
     dfree(C.u);
     dfree(C.tab);
+    dfree(C.tabf);
     dfree(C.sig);
     dfree(C.gl);
     dfree(C.win_mem);
+    dfree(C.halo_slots[0]);
+    dfree(C.halo_slots[1]);
     dfree(C.adj_mem);
     dfree(C.plane64);
     dfree(C.red);
@@ -295,7 +307,7 @@ int sweep(void* u, int parity, bool full = false) {
     const int rowbase = parity == 0 ? 0 : full && !C.aniso ? pm::kTabOddFull : 8;
     const pm::Aniso an{C.aniso ? C.gl : nullptr, tau};
     const pm::StateOffs so{C.half(1 - parity), C.half(parity), C.half(parity), 0, 0};
-    HIPCHK(pm::launch_sweep_win(C.prec, u, so, C.tab, rowbase, an, C.win[parity], C.g, C.stream()));
+    HIPCHK(pm::launch_sweep_win(C.prec, u, so, C.tab, C.tabf, rowbase, an, C.win[parity], C.g, C.stream()));
     if (C.timing) {
         HIPCHK(hipEventRecord(b, C.stream()));
         C.ev[parity].push_back({a, b});
@@ -331,6 +343,39 @@ int run_steps(void* u, long long n, bool merged) {
         if ((rc = sweep(u, 1, s + 1 < n))) return rc;
     }
     return PM_OK;
+}
+
+// Halo faces of a sweep of parity p when the box is one GPU's share of a
+// split grid.  The sweep reads each dual moment (parity 1 - p) at one
+// neighbour per direction d: forward (c + e_d) when the moment is
+// unstaggered in d, backward when it is staggered.  So the -d neighbour
+// needs this box's layer 0 of the dual moments unstaggered in d (face d-)
+// and the +d neighbour its last layer of those staggered in d (face d+).
+// Packing order: faces x-, x+, y-, y+, z-, z+; in a face the moments by
+// storage slot, then the face cells with the two other coordinates in
+// memory order.
+HaloPlan halo_plan(const pm::Layout& L, int nx, int ny, int nz, int parity) {
+    HaloPlan hp;
+    const long long n[3] = {nx, ny, nz};
+    long long end = 0;
+    for (int f = 0; f < 6; ++f) {
+        const int d = f >> 1, side = f & 1;
+        hp.hf.slot0[f] = (int)hp.slots.size();
+        for (int s = 0; s < L.V; ++s) {
+            const int i = L.moment_of[s];
+            int l, m;
+            pm::moment_lm(i, l, m);
+            if ((l & 1) != 1 - parity) continue;
+            if (((pm::grid_bits(l, m) >> d) & 1) != side) continue;
+            hp.slots.push_back(s);
+        }
+        const long long cnt = (long long)hp.slots.size() - hp.hf.slot0[f];
+        hp.hf.area[f] = n[(d + 1) % 3] * n[(d + 2) % 3];
+        hp.hf.layer[f] = side ? (int)n[d] - 1 : 0;
+        end += cnt * hp.hf.area[f];
+        hp.hf.end[f] = end;
+    }
+    return hp;
 }
 
 int check_moment(int moment) {
@@ -436,7 +481,8 @@ int pm_init_cells(int N, int nx, int ny, int nz, double dx, double dy, double dz
     {
         size_t fr = 0, tot = 0;
         hipError_t me = hipMemGetInfo(&fr, &tot);
-        const size_t need = C.state_bytes() + sizeof(double) * (pm::kTabRows + 3) * (size_t)ncell;
+        const size_t need = C.state_bytes() + sizeof(double) * (pm::kTabRows + 3) * (size_t)ncell +
+                            (C.prec != PM_FP64 && !C.aniso ? sizeof(float) * pm::kTabRows * (size_t)ncell : 0);
         if (me != hipSuccess) {
             release();
             return fail(PM_EDEVICE, std::string("hipMemGetInfo: ") + hipGetErrorString(me));
@@ -450,11 +496,14 @@ int pm_init_cells(int N, int nx, int ny, int nz, double dx, double dy, double dz
     TRY(dmalloc(&C.u, C.state_bytes(), "state"));
     TRY(dmalloc(&C.tab, sizeof(double) * pm::kTabRows * (size_t)ncell, "tables"));
     TRY(dmalloc(&C.sig, sizeof(double) * 2 * (size_t)ncell, "sigma"));
+    const bool ftab = C.prec != PM_FP64 && !C.aniso;
+    if (ftab) TRY(dmalloc(&C.tabf, sizeof(float) * pm::kTabRows * (size_t)ncell, "float tables"));
     if (C.aniso) TRY(dmalloc(&C.gl, sizeof(double) * gl.size(), "scattering moments"));
     TRY(dmalloc(&C.plane64, sizeof(double) * (size_t)ncell, "plane"));
     TRY(dmalloc(&C.red, sizeof(double) * (C.npart + 1), "reduction"));
     TRY(dmalloc(&C.redc, sizeof(unsigned long long) * (C.npart + 1), "reduction"));
     TRY(build_window_tables(pm::win_depth(C.prec, nx, N), C.win, &C.win_mem));
+
     if (C.prec != PM_BF16 && pm::adj_depth(C.prec) != pm::win_depth(C.prec, nx, N)) {
         TRY(build_window_tables(pm::adj_depth(C.prec), C.wadj, &C.adj_mem));
     } else {
@@ -466,6 +515,14 @@ int pm_init_cells(int N, int nx, int ny, int nz, double dx, double dy, double dz
         if (err == hipSuccess) return PM_OK;
         return fail(PM_EDEVICE, std::string(what) + ": " + hipGetErrorString(err));
     };
+    for (int p = 0; p < 2; ++p) {
+        C.halo[p] = halo_plan(C.L, nx, ny, nz, p);
+        TRY(dmalloc(&C.halo_slots[p], sizeof(int) * std::max<size_t>(1, C.halo[p].slots.size()), "halo faces"));
+        if (!C.halo[p].slots.empty())
+            TRY(dev(hipMemcpyAsync(C.halo_slots[p], C.halo[p].slots.data(), sizeof(int) * C.halo[p].slots.size(),
+                                   hipMemcpyHostToDevice, C.stream()),
+                    "copy halo faces"));
+    }
     TRY(dev(hipMemcpyAsync(C.sig, sigma_a, sizeof(double) * ncell, hipMemcpyHostToDevice, s), "copy sigma_a"));
     TRY(dev(hipMemcpyAsync(C.sig + ncell, sigma_s, sizeof(double) * ncell, hipMemcpyHostToDevice, s), "copy sigma_s"));
     if (q) TRY(dev(hipMemcpyAsync(C.plane64, q, sizeof(double) * ncell, hipMemcpyHostToDevice, s), "copy q"));
@@ -474,6 +531,7 @@ int pm_init_cells(int N, int nx, int ny, int nz, double dx, double dy, double dz
                 "copy scattering moments"));
     TRY(dev(pm::launch_tables(C.sig, C.sig + ncell, q ? C.plane64 : nullptr, C.tab, C.g, dt, C.aniso, s),
             "tables"));
+    if (ftab) TRY(dev(pm::launch_tables_f32(C.tab, C.tabf, ncell, s), "float tables"));
     TRY(dev(pm::launch_fill_zero(C.u, (long long)C.state_bytes(), s), "zero state"));
     TRY(dev(hipStreamSynchronize(s), "sync"));
 #undef TRY
@@ -665,7 +723,7 @@ int grad_impl(const double* dL_du0, double* dsa, double* dss, bool dev) {
     auto fwd = [&](int p, long long src, long long tin, long long tout) -> hipError_t {
         if (C.win[p].npass == 0) return hipSuccess;  // a parity without moments (N = 0, odd)
         const pm::Aniso an{C.aniso ? C.gl : nullptr, p ? 0.5 * C.dt : C.dt};
-        return pm::launch_sweep_win(C.prec, pool, pm::StateOffs{src, tin, tout, 0, 0}, C.tab,
+        return pm::launch_sweep_win(C.prec, pool, pm::StateOffs{src, tin, tout, 0, 0}, C.tab, C.tabf,
                                     p ? 8 : 0, an, C.win[p], C.g, s);
     };
     // transpose of the substep of parity p whose old state has halves (E, O)
@@ -836,6 +894,57 @@ int pm_moment_slot(int N, int moment) {
     if (N < 0 || N > PM_N_MAX) return fail(PM_EINVAL, "N must be in [0, 63]");
     if (moment < 0 || moment >= (N + 1) * (N + 1)) return fail(PM_EINVAL, "moment out of range");
     return pm::make_layout(N).slot_of[moment];
+}
+
+long long pm_halo_plan(int N, int nx, int ny, int nz, int parity, long long* moment,
+                       long long* cell, long long cap) {
+    if (N < 0 || N > PM_N_MAX) return fail(PM_EINVAL, "N must be in [0, 63]");
+    if (nx < 1 || ny < 1 || nz < 1) return fail(PM_EINVAL, "grid sizes must be >= 1");
+    if (parity != 0 && parity != 1) return fail(PM_EINVAL, "parity must be 0 or 1");
+    if (cap < 0) return fail(PM_EINVAL, "cap < 0");
+    const pm::Layout L = pm::make_layout(N);
+    const HaloPlan hp = halo_plan(L, nx, ny, nz, parity);
+    const long long total = hp.hf.end[5];
+    if (moment || cell) {
+        long long k = 0;
+        for (int f = 0; f < 6 && k < cap; ++f) {
+            const int d = f >> 1, layer = hp.hf.layer[f];
+            const long long cnt = f < 5 ? hp.hf.slot0[f + 1] - hp.hf.slot0[f]
+                                        : (long long)hp.slots.size() - hp.hf.slot0[f];
+            for (long long j = 0; j < cnt && k < cap; ++j)
+                for (long long a = 0; a < hp.hf.area[f] && k < cap; ++a, ++k) {
+                    long long c;
+                    if (d == 0)
+                        c = layer + (long long)nx * a;
+                    else if (d == 1)
+                        c = (a % nx) + (long long)nx * (layer + (long long)ny * (a / nx));
+                    else
+                        c = a + (long long)nx * ny * layer;
+                    if (moment) moment[k] = L.moment_of[hp.slots[hp.hf.slot0[f] + j]];
+                    if (cell) cell[k] = c;
+                }
+        }
+    }
+    return total;
+}
+
+namespace {
+
+int halo_move(int parity, void* buf, bool unpack) {
+    if (!C.live) return fail(PM_ESTATE, "no context: call pm_init first");
+    if (parity != 0 && parity != 1) return fail(PM_EINVAL, "parity must be 0 or 1");
+    if (!buf) return fail(PM_EINVAL, "buffer is NULL");
+    const HaloPlan& hp = C.halo[parity];
+    HIPCHK(pm::launch_halo(C.prec, unpack, C.u, buf, C.halo_slots[parity], hp.hf, C.g, C.stream()));
+    return PM_OK;
+}
+
+}  // namespace
+
+int pm_halo_pack(int parity, void* device_buf) { return halo_move(parity, device_buf, false); }
+
+int pm_halo_unpack(int parity, const void* device_buf) {
+    return halo_move(parity, const_cast<void*>(device_buf), true);
 }
 
 long long pm_device_bytes(void) {

@@ -71,6 +71,9 @@ struct Aniso {
 // (s in storage order) and row kTabQ holds q; the other rows are unused.
 hipError_t launch_tables(const double* sa, const double* ss, const double* q, double* tab,
                          GridDesc g, double dt, bool aniso, hipStream_t st);
+// float copy of the isotropic tables: gamma = 1 - alpha in every alpha row,
+// the other rows rounded (kTabRows rows of n values)
+hipError_t launch_tables_f32(const double* tab, float* tabf, long long n, hipStream_t st);
 
 // Planes of a sweep, as element offsets from one base pointer (the pool):
 // src = first plane of the dual parity (the sources), tin / tout = first
@@ -85,8 +88,11 @@ struct StateOffs {
 // rowbase: table row of alpha for the first target grid of the parity
 // (0 for the even sweep, 8 for an odd half step, kTabOddFull for a full one;
 // with anisotropic scattering 0 or 8, the substep length coming from an.tau).
-hipError_t launch_sweep_win(int prec, void* pool, StateOffs so, const double* tab, int rowbase,
-                            Aniso an, WinArgs a, GridDesc g, hipStream_t st);
+// tabf: float copy of the tables (launch_tables_f32) read by the FP32
+// update of float and bfloat16 storage with isotropic scattering (nullptr
+// otherwise).
+hipError_t launch_sweep_win(int prec, void* pool, StateOffs so, const double* tab, const float* tabf,
+                            int rowbase, Aniso an, WinArgs a, GridDesc g, hipStream_t st);
 
 // Transposed substep on the window streams.  side 0 (target side): so.src /
 // so.aux = dual / target half of the old state, tin = tout = cotangent lam
@@ -118,5 +124,18 @@ hipError_t launch_grad_final(const double* grad, const double* tab, const double
                              bool aniso, hipStream_t st);
 
 hipError_t launch_fill_zero(void* p, long long bytes, hipStream_t st);
+
+// Halo faces of a sweep, in packing order x-, x+, y-, y+, z-, z+: face f
+// holds the layer `layer[f]` of the moments whose slots are
+// slots[slot0[f] ...] (area[f] cells each); end[f] = packed elements of
+// faces 0..f.
+struct HaloFaces {
+    long long end[6];
+    long long area[6];
+    int layer[6];
+    int slot0[6];
+};
+hipError_t launch_halo(int prec, bool unpack, void* u, void* buf, const int* slots, HaloFaces hf,
+                       GridDesc g, hipStream_t st);
 
 }  // namespace pm

@@ -47,6 +47,9 @@
 #ifndef PM_WIN_K16
 #define PM_WIN_K16 3
 #endif
+#ifndef PM_WIN_K64R
+#define PM_WIN_K64R 3   // FP64 where waves do not hold whole rows
+#endif
 
 namespace pm {
 
@@ -259,6 +262,28 @@ __global__ void k_tables_aniso(const double* __restrict__ sa, const double* __re
     tab[(long long)kTabQ * g.ncell + c] = q ? q[c] : 0.0;
 }
 
+// Float copy of the tables for the FP32 update of float and bfloat16
+// storage: every alpha row holds gamma = 1 - alpha instead (the update is
+// u - gamma u + beta (q - S)), so that rounding the factor to float moves
+// the per-step decay by a relative 2^-24 of gamma, not of alpha: no
+// systematic drift of order steps * 2^-24 over a run.
+__global__ void k_tables_f32(const double* __restrict__ tab, float* __restrict__ tabf,
+                             long long n) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (long long)kTabRows * n) return;
+    const int row = (int)(i / n);
+    const bool alpha = (row < kTabQ && (row & 1) == 0) || (row > kTabQ && ((row - kTabOddFull) & 1) == 0);
+    const double v = tab[i];
+    tabf[i] = (float)(alpha ? 1.0 - v : v);
+}
+
+hipError_t launch_tables_f32(const double* tab, float* tabf, long long n, hipStream_t st) {
+    const long long tot = (long long)kTabRows * n;
+    hipLaunchKernelGGL(k_tables_f32, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, tab,
+                       tabf, n);
+    return hipGetLastError();
+}
+
 hipError_t launch_tables(const double* sa, const double* ss, const double* q, double* tab,
                          GridDesc g, double dt, bool aniso, hipStream_t st) {
     const int B = 256;
@@ -336,12 +361,19 @@ __device__ __forceinline__ typename Pack<T, CPL>::V pack(const double (&v)[CPL])
     return r;
 }
 
-// bfloat16 storage from float values (the FP32 update of BF16 storage)
+// float or bfloat16 storage from float values (the FP32 update)
 template <class T, int CPL>
 __device__ __forceinline__ typename Pack<T, CPL>::V pack_f(const float (&v)[CPL]) {
-    static_assert(std::is_same<T, bf16s>::value, "float update only for bfloat16 storage");
+    static_assert(!std::is_same<T, double>::value, "float update only for float and bfloat16 storage");
     typename Pack<T, CPL>::V r;
-    if constexpr (CPL == 1) {
+    if constexpr (std::is_same<T, float>::value) {
+        if constexpr (CPL == 1) {
+            r = v[0];
+        } else {
+#pragma unroll
+            for (int k = 0; k < CPL; ++k) r[k] = v[k];
+        }
+    } else if constexpr (CPL == 1) {
         r = (uint16_t)(bf_pack2(v[0], 0.0f) & 0xffffu);
     } else if constexpr (CPL == 2) {
         r = bf_pack2(v[0], v[1]);
@@ -370,6 +402,12 @@ struct LaneNbr {
     int yp, ym, zp, zm; // row offsets of the y / z neighbours: forward, backward
 };
 
+// How a sweep gets the x neighbour outside a lane's own cells:
+//   kXLoad   loaded by every lane (any tiling);
+//   kXRow    whole-row waves (64 CPL cells = nx): by lane rotation, the
+//            periodic wrap included.
+enum XMode { kXLoad = 0, kXRow = 1 };
+
 // Wavefront rotations by one lane (DPP wave_rol:1 / wave_ror:1): lane i
 // receives the value of lane i + 1 (next) or i - 1 (prev), modulo 64.
 // Every lane of the wave must be active; every lane then reads a valid lane,
@@ -392,10 +430,10 @@ template <bool NEXT> __device__ __forceinline__ uint16_t rot(uint16_t v) {
     return (uint16_t)(NEXT ? rot_next(v) : rot_prev(v));
 }
 
-// XROT: every wave holds one whole row (64 lanes x CPL cells = nx), so the
+// kXRow: every wave holds one whole row (64 lanes x CPL cells = nx), so the
 // x neighbour outside a lane's cells, periodic wrap included, is held by the
 // next or previous lane and comes by a rotation instead of a load.
-template <class T, int CPL, bool XROT>
+template <class T, int CPL, int XM>
 __device__ __forceinline__ void win_fetch(Raw<T, CPL>& r, const T* __restrict__ u, int2 d,
                                           const LaneNbr& nb, long long ps) {
     using V = typename Pack<T, CPL>::V;
@@ -405,7 +443,7 @@ __device__ __forceinline__ void win_fetch(Raw<T, CPL>& r, const T* __restrict__ 
         r.c = *(const V*)p;
         r.y = *(const V*)(p + ((d.y & 2) ? nb.ym : nb.yp));
         r.z = *(const V*)(p + ((d.y & 4) ? nb.zm : nb.zp));
-        if (!XROT) r.xe = *(const S1*)(p + ((d.y & 1) ? nb.xem : nb.xep));
+        if constexpr (XM == kXLoad) r.xe = *(const S1*)(p + ((d.y & 1) ? nb.xem : nb.xep));
     } else {
         r.c = V{};
         r.y = V{};
@@ -429,66 +467,57 @@ __device__ __forceinline__ void win_fetch(Raw<T, CPL>& r, const T* __restrict__ 
 constexpr int kXcds = 8;
 
 struct TileMap {
-    int sw;        // segment width in cells, or 0 for linear tiles
+    int sw;        // segment width in cells; 0 for linear tiles; -1 for chunk
+                   // tiles (nseg = 1, nty = chunks of 64 cells per x-y plane)
     int nseg;      // segments per row
     int nty, ntz;  // tiles per direction
+    int pg;        // adjacent passes dispatched together (1: pass-major)
+    int gy, gz;    // tile blocks of gy y-tiles x gz z-tiles (gz = 0: none)
 };
 
-// Tile order within the contiguous range of an XCD (segment tiles only).
-// PM_TILE_GZ > 0 groups the tiles in blocks of PM_TILE_GY y-tiles x
-// PM_TILE_GZ z-tiles (segments fastest, then y, then z inside a block;
-// blocks by y within a z-group), so the workgroups resident at one time
-// cover a compact (y, z) block and more of their one-sided neighbour rows
-// are rows that a resident sibling reads.  0 keeps segments fastest, then
-// y, then z over the whole grid.
-#ifndef PM_TILE_GZ
-#define PM_TILE_GZ 0
-#endif
-#ifndef PM_TILE_GY
-#define PM_TILE_GY 4
-#endif
-// Passes dispatched together: 1 = pass-major (every tile of the heaviest
-// pass first); G > 1 interleaves G adjacent passes of the same tile, so the
-// source degree two adjacent passes share is read by both at about the same
-// time.
-#ifndef PM_PASS_GROUP
-#define PM_PASS_GROUP 1
-#endif
-
+// Tile order within the contiguous range of an XCD.  With m.gz > 0 the
+// tiles go in blocks of m.gy y-tiles x m.gz z-tiles (segments fastest, then
+// y, then z inside a block; blocks by y within a z-group), so the
+// workgroups resident at one time cover a compact (y, z) block and more of
+// their one-sided neighbour rows are rows a resident sibling reads;
+// otherwise segments fastest, then y, then z over the whole grid.
 __device__ __forceinline__ long long tile_order(const TileMap& m, long long t) {
-    if (PM_TILE_GZ <= 0 || m.sw == 0) return t;
+    if (m.gz <= 0 || m.sw == 0) return t;
     const long long A = (long long)m.nseg * m.nty;
-    const long long zg = t / (A * PM_TILE_GZ);
-    long long r = t - zg * A * PM_TILE_GZ;
-    const int gz = min(PM_TILE_GZ, m.ntz - (int)zg * PM_TILE_GZ);
-    const long long B = (long long)m.nseg * PM_TILE_GY * gz;
+    const long long zg = t / (A * m.gz);
+    long long r = t - zg * A * m.gz;
+    const int gz = min(m.gz, m.ntz - (int)zg * m.gz);
+    const long long B = (long long)m.nseg * m.gy * gz;
     const long long yb = r / B;
     r -= yb * B;
-    const int gy = min(PM_TILE_GY, m.nty - (int)yb * PM_TILE_GY);
+    const int gy = min(m.gy, m.nty - (int)yb * m.gy);
     const long long seg = r % m.nseg;
     r /= m.nseg;
-    const long long ty = yb * PM_TILE_GY + r % gy;
-    const long long tz = zg * PM_TILE_GZ + r / gy;
+    const long long ty = yb * m.gy + r % gy;
+    const long long tz = zg * m.gz + r / gy;
     return seg + m.nseg * (ty + (long long)m.nty * tz);
 }
 
 // Workgroup id -> (tile, pass); false for an id past the grid.  Workgroups
 // are dispatched round-robin over the XCDs (id mod 8); each XCD gets a
-// contiguous range of per_xcd tiles.
+// contiguous range of per_xcd tiles.  m.pg = 1: pass-major (every tile of
+// the heaviest pass first); m.pg = G > 1: G adjacent passes of a tile are
+// dispatched together, so the source degree two adjacent passes share is
+// read by both at about the same time.
 __device__ __forceinline__ bool block_work(const TileMap& m, int npass, int per_xcd,
                                            long long ntile, long long& tile, int& pass) {
     const int xcd = blockIdx.x % kXcds;
     const int j = blockIdx.x / kXcds;
     int ti;
-    if (PM_PASS_GROUP <= 1) {
+    if (m.pg <= 1) {
         ti = j % per_xcd;
         pass = npass - 1 - j / per_xcd;
     } else {
-        const int q = j / (per_xcd * PM_PASS_GROUP);
-        const int r = j - q * per_xcd * PM_PASS_GROUP;
-        const int gq = min(PM_PASS_GROUP, npass - q * PM_PASS_GROUP);
+        const int q = j / (per_xcd * m.pg);
+        const int r = j - q * per_xcd * m.pg;
+        const int gq = min(m.pg, npass - q * m.pg);
         ti = r / gq;
-        pass = npass - 1 - q * PM_PASS_GROUP - r % gq;
+        pass = npass - 1 - q * m.pg - r % gq;
     }
     const long long t = (long long)xcd * per_xcd + ti;
     if (pass < 0 || t >= ntile) return false;
@@ -503,6 +532,20 @@ __device__ __forceinline__ long long tile_cell(const TileMap& m, long long tile,
         const long long c = (tile * TPB + tid) * CPL;
         live = c < g.ncell;
         return c;
+    }
+    if (m.sw < 0) {
+        // chunk tiles: chunk k of 64 cells of an x-y plane, waves stacked in
+        // z; a wave past the grid takes the last plane and lanes past the
+        // plane's last cell take that cell (valid addresses, not stored)
+        const long long nxy = (long long)g.nx * g.ny;
+        const long long k = tile % m.nty;
+        const int zt = (int)(tile / m.nty);
+        int z = zt * (TPB / 64) + (tid >> 6);
+        long long p = k * 64 + (tid & 63);
+        live = z < g.nz && p < nxy;
+        if (z >= g.nz) z = g.nz - 1;
+        if (p >= nxy) p = nxy - 1;
+        return (long long)z * nxy + p;
     }
     const int ls = m.sw / CPL;  // lanes per segment row
     const long long xs = tile % m.nseg;
@@ -552,9 +595,43 @@ template <> struct MinWaves<float> { static constexpr int v = PM_WPE32; };
 #ifndef PM_WPE64_DUAL
 #define PM_WPE64_DUAL 4
 #endif
-template <class T, int MODE, bool ANI, bool XROT>
+// Unused rows added to the LDS table array (a cap on resident workgroups
+// for tuning; 0 in use).
+#ifndef PM_TL_PAD_ROWS
+#define PM_TL_PAD_ROWS 0
+#endif
+// Dispatch of chunk tiles: groups of adjacent passes and tile blocks
+// (chunks x z-tiles; see tile_order and block_work).
+#ifndef PM_CHUNK_PASS_GROUP
+#define PM_CHUNK_PASS_GROUP 3
+#endif
+#ifndef PM_CHUNK_GY
+#define PM_CHUNK_GY 32
+#endif
+#ifndef PM_CHUNK_GZ
+#define PM_CHUNK_GZ 4
+#endif
+// Chunk tiles (1): rows of nx > 64 cells whose x-y planes hold whole waves
+// are tiled by chunks of 64 consecutive cells of a plane (rows cross chunk
+// boundaries; x neighbours loaded), so every plane access of a wave is one
+// contiguous 64-cell piece; 0 keeps 16- or 32-lane row segments there.
+// PM_CHUNK_RAGGED (1) uses them also where a plane ends inside a chunk
+// (its last chunk is partly empty) instead of linear tiles: P19 at 500^3,
+// FP32 sweep 80.2 vs 87.5 ms.
+#ifndef PM_CHUNK_TILES
+#define PM_CHUNK_TILES 1
+#endif
+#ifndef PM_CHUNK_RAGGED
+#define PM_CHUNK_RAGGED 1
+#endif
+// resident waves asked for the FP64 forward sweeps with loaded x neighbours
+#ifndef PM_WPE64N
+#define PM_WPE64N 1
+#endif
+template <class T, int MODE, bool ANI, int XM>
 constexpr int min_waves() {
-    if (MODE == kFwd) return XROT && !ANI ? MinWaves<T>::v : 1;
+    if (MODE == kFwd && XM == kXLoad && !ANI && std::is_same<T, double>::value) return PM_WPE64N;
+    if (MODE == kFwd) return XM == kXRow && !ANI ? MinWaves<T>::v : 1;
     if (!std::is_same<T, double>::value || ANI) return 1;
     return MODE == kAdjTgt ? PM_WPE64_ADJ : PM_WPE64_DUAL;
 }
@@ -564,13 +641,13 @@ constexpr int min_waves() {
 // the means of sigma_a and sigma_s; the decay factors of every (target
 // degree, grid) pair of the pass are formed once per cell from
 // c_l = mean sigma_a + (1 - g_l) mean sigma_s with the per-degree moments gl
-// and the substep length tau, and kept in LDS.  XROT: whole-row waves (see
-// win_fetch), in every mode: the push phase is the same forward-shaped
+// and the substep length tau, and kept in LDS.  XM: how the x neighbours
+// come (XMode), in every mode: the push phase is the same forward-shaped
 // stencil for the transposed sweeps.
-template <class T, int K, int TPB, int CPL, int MODE, bool ANI, bool XROT>
-__global__ void __launch_bounds__(TPB, (min_waves<T, MODE, ANI, XROT>()))
+template <class T, int K, int TPB, int CPL, int MODE, bool ANI, int XM>
+__global__ void __launch_bounds__(TPB, (min_waves<T, MODE, ANI, XM>()))
 k_sweep_win(T* __restrict__ pool, StateOffs so, double* __restrict__ gp,
-            const double* __restrict__ tab,
+            const double* __restrict__ tab, const float* __restrict__ tabf,
             const int2* __restrict__ src, const int2* __restrict__ tgt,
             const typename Acc<T>::type* __restrict__ coef, const double* __restrict__ gl,
             double tau, int rowbase, int N, int parity, int npass, int per_xcd, long long ntile,
@@ -591,7 +668,8 @@ k_sweep_win(T* __restrict__ pool, StateOffs so, double* __restrict__ gp,
     const long long cl = tile_cell<TPB, CPL>(tm, tile, threadIdx.x, g, live);
     LaneNbr nb;
     {
-        const long long c = live ? cl : g.ncell - CPL;
+        // chunk tiles give every wave a valid chunk, also past the grid
+        const long long c = (live || tm.sw < 0) ? cl : g.ncell - CPL;
         const Nbr n0 = neighbours(c, g);
         const int x0 = (int)(c % g.nx);
         nb.c0 = c;
@@ -602,12 +680,18 @@ k_sweep_win(T* __restrict__ pool, StateOffs so, double* __restrict__ gp,
         nb.zp = n0.off[4];
         nb.zm = n0.off[5];
     }
-    if constexpr (XROT) {
+    if constexpr (XM == kXRow) {
         // a wave is one row (or, past the grid, one cell): its y and z
         // neighbour rows are the same for every lane, so the offsets and the
         // choice between them live in scalar registers
         nb.yp = __builtin_amdgcn_readfirstlane(nb.yp);
         nb.ym = __builtin_amdgcn_readfirstlane(nb.ym);
+        nb.zp = __builtin_amdgcn_readfirstlane(nb.zp);
+        nb.zm = __builtin_amdgcn_readfirstlane(nb.zm);
+    }
+    if (tm.sw < 0) {
+        // chunk tiles: a wave is 64 consecutive cells of one x-y plane, so
+        // its z neighbour offsets are wave-uniform
         nb.zp = __builtin_amdgcn_readfirstlane(nb.zp);
         nb.zm = __builtin_amdgcn_readfirstlane(nb.zm);
     }
@@ -617,12 +701,13 @@ k_sweep_win(T* __restrict__ pool, StateOffs so, double* __restrict__ gp,
     // ANI: target degree t and grid f in rows 2 (4 t + f), 2 (4 t + f) + 1,
     // q in row 8 K
     constexpr int kRowQ = ANI ? 8 * K : 10;
-    // BF16 storage is a storage form: its update runs in FP32, with the
-    // float64 factors rounded to float once when staged (half the LDS, and
-    // no FP64 arithmetic per cell; its own rounding, 2^-9, is far larger)
-    constexpr bool kF32Update = std::is_same<T, bf16s>::value;
+    // FP32 and BF16 storage: the forward update runs in FP32 from factors
+    // rounded to float (gamma = 1 - alpha and beta, computed in FP64): half
+    // the LDS and, isotropic, half the table reads (float tables); the
+    // transposed sweeps keep FP64 factors
+    constexpr bool kF32Update = !std::is_same<T, double>::value && MODE == kFwd;
     using TabT = typename std::conditional<kF32Update, float, double>::type;
-    __shared__ TabT tl[kRowQ + 1][TPB * CPL];
+    __shared__ TabT tl[kRowQ + 1 + PM_TL_PAD_ROWS][TPB * CPL];
     const int tid = threadIdx.x;
     const int MU1 = N + 3;  // source columns 0..N+1 and an empty column N+2
     const int L0 = parity + 2 * K * pass;
@@ -638,7 +723,7 @@ k_sweep_win(T* __restrict__ pool, StateOffs so, double* __restrict__ gp,
                     if (L0 + 2 * t > N) continue;
                     double a, b;
                     decay(ma + (1.0 - gl[L0 + 2 * t]) * ms, tau, a, b);
-                    tl[2 * (4 * t + f)][tid * CPL + k] = a;
+                    tl[2 * (4 * t + f)][tid * CPL + k] = kF32Update ? 1.0 - a : a;
                     tl[2 * (4 * t + f) + 1][tid * CPL + k] = b;
                 }
             }
@@ -647,7 +732,8 @@ k_sweep_win(T* __restrict__ pool, StateOffs so, double* __restrict__ gp,
         for (int f = 0; f < 8; ++f)
 #pragma unroll
             for (int k = 0; k < CPL; ++k)
-                tl[f][tid * CPL + k] = tab[(long long)(rowbase + f) * g.ncell + nb.c0 + k];
+                tl[f][tid * CPL + k] = kF32Update ? (TabT)tabf[(long long)(rowbase + f) * g.ncell + nb.c0 + k]
+                                                  : (TabT)tab[(long long)(rowbase + f) * g.ncell + nb.c0 + k];
     }
     // kAdjTgt gradient sums: per coefficient set (isotropic), or per grid
     // with respect to the means of sigma_a (ga) and sigma_s (gb) (ANI)
@@ -657,10 +743,13 @@ k_sweep_win(T* __restrict__ pool, StateOffs so, double* __restrict__ gp,
 #pragma unroll
         for (int k = 0; k < CPL; ++k) {
             if (!ANI) {
-                tl[8][tid * CPL + k] = tab[(long long)kTabMom0 * g.ncell + nb.c0 + k];
-                tl[9][tid * CPL + k] = tab[(long long)(kTabMom0 + 1) * g.ncell + nb.c0 + k];
+                tl[8][tid * CPL + k] = kF32Update ? (TabT)tabf[(long long)kTabMom0 * g.ncell + nb.c0 + k]
+                                                  : (TabT)tab[(long long)kTabMom0 * g.ncell + nb.c0 + k];
+                tl[9][tid * CPL + k] = kF32Update ? (TabT)tabf[(long long)(kTabMom0 + 1) * g.ncell + nb.c0 + k]
+                                                  : (TabT)tab[(long long)(kTabMom0 + 1) * g.ncell + nb.c0 + k];
             }
-            tl[kRowQ][tid * CPL + k] = tab[(long long)kTabQ * g.ncell + nb.c0 + k];
+            tl[kRowQ][tid * CPL + k] = (kF32Update && !ANI) ? (TabT)tabf[(long long)kTabQ * g.ncell + nb.c0 + k]
+                                                            : (TabT)tab[(long long)kTabQ * g.ncell + nb.c0 + k];
         }
     }
     const int mumax = min(N, L0 + 2 * (K - 1));  // largest target |m| in the pass
@@ -685,7 +774,7 @@ k_sweep_win(T* __restrict__ pool, StateOffs so, double* __restrict__ gp,
 #pragma unroll
     for (int b = 0; b <= K; ++b)
 #pragma unroll
-        for (int ty = 0; ty < 2; ++ty) win_fetch<T, CPL, XROT>(R[b][ty], sv, sd[b * 2 + ty], nb, ps);
+        for (int ty = 0; ty < 2; ++ty) win_fetch<T, CPL, XM>(R[b][ty], sv, sd[b * 2 + ty], nb, ps);
 #pragma unroll
     for (int w = 0; w < 3; ++w)
 #pragma unroll
@@ -711,7 +800,7 @@ k_sweep_win(T* __restrict__ pool, StateOffs so, double* __restrict__ gp,
                 unpack<T, CPL, A>(R[b][ty].z, vz);
                 const bool back = e.y & 1;
                 A xv;
-                if constexpr (XROT) {
+                if constexpr (XM != kXLoad) {
                     // first cell of the next lane, or last cell of the previous one
                     using S1 = typename Pack<T, CPL>::S1;
                     S1 first, last;
@@ -748,7 +837,7 @@ k_sweep_win(T* __restrict__ pool, StateOffs so, double* __restrict__ gp,
                 for (int k = 0; k < CPL; ++k) asm volatile("" ::"v"(dx[k]), "v"(dy[k]), "v"(dz[k]));
                 // the stream ends with an empty column, so the next one can
                 // always be requested
-                win_fetch<T, CPL, XROT>(R[b][ty], sv, sdn[b * 2 + ty], nb, ps);
+                win_fetch<T, CPL, XM>(R[b][ty], sv, sdn[b * 2 + ty], nb, ps);
                 if (e.x < 0) continue;
 #pragma unroll
                 for (int side = 0; side < 2; ++side) {
@@ -811,9 +900,11 @@ k_sweep_win(T* __restrict__ pool, StateOffs so, double* __restrict__ gp,
                         float nf[CPL];
 #pragma unroll
                         for (int k = 0; k < CPL; ++k) {
+                            // u - gamma u + beta (q - S)
                             const float q = m0 ? (float)tl[kRowQ][tid * CPL + k] : 0.0f;
-                            nf[k] = (float)tl[ra][tid * CPL + k] * (float)old[k] +
-                                    (float)tl[ra + 1][tid * CPL + k] * (q - (float)S[0][t][ty][k]);
+                            const float uo = (float)old[k];
+                            nf[k] = __builtin_fmaf((float)tl[ra + 1][tid * CPL + k], q - (float)S[0][t][ty][k],
+                                                   __builtin_fmaf(-(float)tl[ra][tid * CPL + k], uo, uo));
                         }
                         if (live) __builtin_nontemporal_store(pack_f<T, CPL>(nf), (V*)ut);
                         continue;
@@ -885,7 +976,7 @@ k_sweep_win(T* __restrict__ pool, StateOffs so, double* __restrict__ gp,
         // as z neighbours were just read by its sibling and are still cached
         // (+1.6-2% FP64, +0.5% FP32; flat for loaded x neighbours).  Every
         // wave of a workgroup runs the same pass, so all reach it equally often.
-        if constexpr (XROT) __syncthreads();
+        if constexpr (XM == kXRow) __syncthreads();
     }
     if constexpr (MODE == kAdjTgt) {
         // gradient rows of this pass (2 s for alpha, 2 s + 1 for beta, s the
@@ -912,14 +1003,15 @@ k_sweep_win(T* __restrict__ pool, StateOffs so, double* __restrict__ gp,
 static_assert(PM_ADJ_K64 >= 2 && PM_ADJ_K64 <= 3 && PM_ADJ_K32 >= 2 && PM_ADJ_K32 <= 3 &&
                   PM_WIN_K64 >= 2 && PM_WIN_K64 <= PM_MAX_K && PM_WIN_K32 >= 2 &&
                   PM_WIN_K32 <= PM_MAX_K && PM_WIN_K32R >= 2 && PM_WIN_K32R <= PM_MAX_K &&
-                  PM_WIN_KLOW >= 2 && PM_WIN_KLOW <= PM_MAX_K && PM_MAX_K <= 4,
+                  PM_WIN_KLOW >= 2 && PM_WIN_KLOW <= PM_MAX_K && PM_MAX_K <= 4 &&
+                  PM_WIN_K64R >= 2 && PM_WIN_K64R <= PM_MAX_K,
               "forward FP64 and FP32 sweeps are instantiated for depths 2..PM_MAX_K, "
               "the transposed ones for 2 and 3");
 
 int win_depth(int prec, int nx, int N) {
     if (prec == kBF16) return PM_WIN_K16;
     if (N <= PM_N_LOW) return PM_WIN_KLOW;
-    if (prec == kF64) return PM_WIN_K64;
+    if (prec == kF64) return nx == 64 ? PM_WIN_K64 : PM_WIN_K64R;
     return nx == 64 ? PM_WIN_K32 : PM_WIN_K32R;  // FP32: one cell per lane
 }
 int adj_depth(int prec) { return prec == kF64 ? PM_ADJ_K64 : prec == kF32 ? PM_ADJ_K32 : PM_WIN_K16; }
@@ -936,11 +1028,12 @@ int adj_depth(int prec) { return prec == kF64 ? PM_ADJ_K64 : prec == kF32 ? PM_A
 #endif
 
 template <class T, int K, int CPL, int MODE, bool ANI>
-static void launch_win_t(T* pool, StateOffs so, double* gp, const double* tab, int rowbase,
+static void launch_win_t(T* pool, StateOffs so, double* gp, const double* tab, const float* tabf,
+                         int rowbase,
                          Aniso an, WinArgs a, GridDesc g, hipStream_t st) {
     using A = typename Acc<T>::type;
     constexpr int TPB = 256 / CPL;
-    TileMap tm{0, 1, 1, 1};
+    TileMap tm{0, 1, 1, 1, 1, 0, 0};
     long long ntile = (g.ncell / CPL + TPB - 1) / TPB;
     int sw = 0;
     for (int lanes = 64; lanes >= 16 && !sw; lanes /= 2)
@@ -955,53 +1048,76 @@ static void launch_win_t(T* pool, StateOffs so, double* gp, const double* tab, i
     const int per_xcd = (int)((ntile + kXcds - 1) / kXcds);
     const unsigned nwg = (unsigned)((long long)kXcds * per_xcd * a.npass);
     // one whole row per wave: x neighbours by lane rotation
-    if (sw == g.nx && g.nx == 64 * CPL)
-        hipLaunchKernelGGL((k_sweep_win<T, K, TPB, CPL, MODE, ANI, true>), dim3(nwg),
-                           dim3(TPB), 0, st, pool, so, gp, tab, a.src, a.tgt, (const A*)a.coef,
+    if (sw == g.nx && g.nx == 64 * CPL) {
+        hipLaunchKernelGGL((k_sweep_win<T, K, TPB, CPL, MODE, ANI, kXRow>), dim3(nwg),
+                           dim3(TPB), 0, st, pool, so, gp, tab, tabf, a.src, a.tgt, (const A*)a.coef,
                            an.gl, an.tau, rowbase, a.N, a.parity, a.npass, per_xcd, ntile, tm, g);
-    else
-        hipLaunchKernelGGL((k_sweep_win<T, K, TPB, CPL, MODE, ANI, false>), dim3(nwg), dim3(TPB),
-                           0, st, pool, so, gp, tab, a.src, a.tgt, (const A*)a.coef, an.gl,
-                           an.tau, rowbase, a.N, a.parity, a.npass, per_xcd, ntile, tm, g);
+        return;
+    }
+    if constexpr (CPL == 1) {
+        // rows of nx > 64 cells whose x-y planes hold whole waves: chunk
+        // tiles, waves stacked in z
+        const long long nxy = (long long)g.nx * g.ny;
+        if (PM_CHUNK_TILES && g.nx > 64 && (nxy % 64 == 0 || (PM_CHUNK_RAGGED && sw == 0))) {
+            // grouped passes and tile blocks: measured on P39 at 160^3
+            // (FP64 -3.6%, FP32 -9.2% sweep time with both); whole-row waves
+            // keep pass-major order, where grouping was slower (64^3: +1.4%
+            // FP64 with groups of 3)
+            TileMap tc{-1, 1, (int)((nxy + 63) / 64), (g.nz + TPB / 64 - 1) / (TPB / 64),
+                       PM_CHUNK_PASS_GROUP, PM_CHUNK_GY, PM_CHUNK_GZ};
+            const long long nt = (long long)tc.nty * tc.ntz;
+            const int px = (int)((nt + kXcds - 1) / kXcds);
+            const unsigned nw = (unsigned)((long long)kXcds * px * a.npass);
+            hipLaunchKernelGGL((k_sweep_win<T, K, TPB, CPL, MODE, ANI, kXLoad>), dim3(nw),
+                               dim3(TPB), 0, st, pool, so, gp, tab, tabf, a.src, a.tgt,
+                               (const A*)a.coef, an.gl, an.tau, rowbase, a.N, a.parity, a.npass,
+                               px, nt, tc, g);
+            return;
+        }
+    }
+    hipLaunchKernelGGL((k_sweep_win<T, K, TPB, CPL, MODE, ANI, kXLoad>), dim3(nwg), dim3(TPB),
+                       0, st, pool, so, gp, tab, tabf, a.src, a.tgt, (const A*)a.coef, an.gl,
+                       an.tau, rowbase, a.N, a.parity, a.npass, per_xcd, ntile, tm, g);
 }
 
 template <class T, int K, int CPL>
-static void launch_fwd(void* pool, StateOffs so, const double* tab, int rowbase, Aniso an,
+static void launch_fwd(void* pool, StateOffs so, const double* tab, const float* tabf, int rowbase, Aniso an,
                        WinArgs a, GridDesc g, hipStream_t st) {
     if (an.gl)
-        launch_win_t<T, K, CPL, kFwd, true>((T*)pool, so, nullptr, tab, rowbase, an, a, g, st);
+        launch_win_t<T, K, CPL, kFwd, true>((T*)pool, so, nullptr, tab, tabf, rowbase, an, a, g, st);
     else
-        launch_win_t<T, K, CPL, kFwd, false>((T*)pool, so, nullptr, tab, rowbase, an, a, g, st);
+        launch_win_t<T, K, CPL, kFwd, false>((T*)pool, so, nullptr, tab, tabf, rowbase, an, a, g, st);
 }
 
-hipError_t launch_sweep_win(int prec, void* pool, StateOffs so, const double* tab, int rowbase,
+hipError_t launch_sweep_win(int prec, void* pool, StateOffs so, const double* tab, const float* tabf,
+                            int rowbase,
                             Aniso an, WinArgs a, GridDesc g, hipStream_t st) {
     if (a.K != win_depth(prec, g.nx, a.N)) return hipErrorInvalidValue;
     // several cells per lane need whole lane groups within every row
     // FP64 and FP32 sweeps come in depths 2 and 3
     if (prec == kF64) {
         if (a.K == 2)
-            launch_fwd<double, 2, 1>(pool, so, tab, rowbase, an, a, g, st);
+            launch_fwd<double, 2, 1>(pool, so, tab, tabf, rowbase, an, a, g, st);
 #if PM_MAX_K >= 4
         else if (a.K == 4)
-            launch_fwd<double, 4, 1>(pool, so, tab, rowbase, an, a, g, st);
+            launch_fwd<double, 4, 1>(pool, so, tab, tabf, rowbase, an, a, g, st);
 #endif
         else
-            launch_fwd<double, 3, 1>(pool, so, tab, rowbase, an, a, g, st);
+            launch_fwd<double, 3, 1>(pool, so, tab, tabf, rowbase, an, a, g, st);
     } else if (prec == kF32) {
         if (a.K == 2)
-            launch_fwd<float, 2, 1>(pool, so, tab, rowbase, an, a, g, st);
+            launch_fwd<float, 2, 1>(pool, so, tab, tabf, rowbase, an, a, g, st);
 #if PM_MAX_K >= 4
         else if (a.K == 4)
-            launch_fwd<float, 4, 1>(pool, so, tab, rowbase, an, a, g, st);
+            launch_fwd<float, 4, 1>(pool, so, tab, tabf, rowbase, an, a, g, st);
 #endif
         else
-            launch_fwd<float, 3, 1>(pool, so, tab, rowbase, an, a, g, st);
+            launch_fwd<float, 3, 1>(pool, so, tab, tabf, rowbase, an, a, g, st);
     } else {
         if (PM_CPL16 > 1 && g.nx % PM_CPL16 == 0)
-            launch_fwd<bf16s, PM_WIN_K16, PM_CPL16>(pool, so, tab, rowbase, an, a, g, st);
+            launch_fwd<bf16s, PM_WIN_K16, PM_CPL16>(pool, so, tab, tabf, rowbase, an, a, g, st);
         else
-            launch_fwd<bf16s, PM_WIN_K16, 1>(pool, so, tab, rowbase, an, a, g, st);
+            launch_fwd<bf16s, PM_WIN_K16, 1>(pool, so, tab, tabf, rowbase, an, a, g, st);
     }
     return hipGetLastError();
 }
@@ -1010,11 +1126,11 @@ template <class T, int K>
 static void launch_adj_t(int side, void* pool, StateOffs so, double* gp, const double* tab,
                          int rowbase, Aniso an, WinArgs a, GridDesc g, hipStream_t st) {
     if (side == 1)
-        launch_win_t<T, K, 1, kAdjDual, false>((T*)pool, so, nullptr, tab, 0, an, a, g, st);
+        launch_win_t<T, K, 1, kAdjDual, false>((T*)pool, so, nullptr, tab, nullptr, 0, an, a, g, st);
     else if (an.gl)
-        launch_win_t<T, K, 1, kAdjTgt, true>((T*)pool, so, gp, tab, rowbase, an, a, g, st);
+        launch_win_t<T, K, 1, kAdjTgt, true>((T*)pool, so, gp, tab, nullptr, rowbase, an, a, g, st);
     else
-        launch_win_t<T, K, 1, kAdjTgt, false>((T*)pool, so, gp, tab, rowbase, an, a, g, st);
+        launch_win_t<T, K, 1, kAdjTgt, false>((T*)pool, so, gp, tab, nullptr, rowbase, an, a, g, st);
 }
 
 hipError_t launch_adj_win(int prec, int side, void* pool, StateOffs so, double* gp,
@@ -1279,6 +1395,64 @@ hipError_t launch_grad_final(const double* grad, const double* tab, const double
     else
         hipLaunchKernelGGL(k_grad_final, dim3(nb), dim3(256), 0, st, grad, tab, sa, ss, dsa, dss,
                            g, dt);
+    return hipGetLastError();
+}
+
+}  // namespace pm
+
+namespace pm {
+
+// ------------------------------------------------------------- halo faces --
+// Gather (pack) or scatter (unpack) of the one-cell halo faces a sweep of
+// one parity needs from its neighbours when the box is split across GPUs:
+// element k of the packed buffer lies in face f (the first face whose end
+// exceeds k), moment j = (k - start) / area of that face (slot slots[...]),
+// face cell (k - start) mod area, the two other coordinates in memory order.
+template <class T, bool UNPACK>
+__global__ void k_halo(T* __restrict__ u, T* __restrict__ buf, const int* __restrict__ slots,
+                       HaloFaces hf, GridDesc g) {
+    const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= hf.end[5]) return;
+    int f = 0;
+#pragma unroll
+    for (int i = 0; i < 5; ++i) f += k >= hf.end[i] ? 1 : 0;
+    const long long start = f == 0 ? 0 : hf.end[f - 1];
+    const long long area = hf.area[f];
+    const long long r = k - start;
+    const long long j = r / area, a = r - j * area;
+    const int d = f >> 1, layer = hf.layer[f];
+    long long c;
+    if (d == 0)
+        c = layer + (long long)g.nx * a;                      // a = y + ny z
+    else if (d == 1)
+        c = (a % g.nx) + (long long)g.nx * (layer + (long long)g.ny * (a / g.nx));  // a = x + nx z
+    else
+        c = a + (long long)g.nx * g.ny * layer;               // a = x + nx y
+    T* p = u + (long long)slots[hf.slot0[f] + j] * g.pstride + c;
+    if (UNPACK)
+        *p = buf[k];
+    else
+        buf[k] = *p;
+}
+
+hipError_t launch_halo(int prec, bool unpack, void* u, void* buf, const int* slots, HaloFaces hf,
+                       GridDesc g, hipStream_t st) {
+    const long long n = hf.end[5];
+    if (n <= 0) return hipSuccess;
+    const dim3 grid((unsigned)((n + 255) / 256)), block(256);
+#define PM_HALO(T)                                                                               \
+    if (unpack)                                                                                  \
+        hipLaunchKernelGGL((k_halo<T, true>), grid, block, 0, st, (T*)u, (T*)buf, slots, hf, g); \
+    else                                                                                         \
+        hipLaunchKernelGGL((k_halo<T, false>), grid, block, 0, st, (T*)u, (T*)buf, slots, hf, g);
+    if (prec == kF64) {
+        PM_HALO(double)
+    } else if (prec == kF32) {
+        PM_HALO(float)
+    } else {
+        PM_HALO(bf16s)
+    }
+#undef PM_HALO
     return hipGetLastError();
 }
 

@@ -42,7 +42,9 @@ def gpu_grad(N, shape, h, dt, sa, ss, q, u0, nsteps, ck, target, prec=0):
 # the grid in the last tile)
 @pytest.mark.parametrize("N,shape,nsteps,ck", [(3, (4, 5, 6), 7, 3), (1, (3, 3, 3), 4, 1),
                                                (2, (1, 2, 9), 5, 5), (3, (2, 3, 70), 3, 2),
-                                               (3, (3, 2, 64), 4, 2), (5, (5, 3, 64), 3, 3)])
+                                               (3, (3, 2, 64), 4, 2), (5, (5, 3, 64), 3, 3),
+                                               # chunk tiles (rows longer than 64 cells)
+                                               (3, (2, 2, 96), 4, 2), (2, (1, 64, 65), 3, 2)])
 def test_grad_matches_numpy_oracle(N, shape, nsteps, ck):
     say("case adjoint small", N, shape, nsteps, ck)
     rng = np.random.default_rng(N * 7 + nsteps)

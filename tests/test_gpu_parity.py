@@ -54,7 +54,11 @@ def test_p3_pulse_full_fp64():
                                      (7, (4, 6, 64)), (5, (2, 3, 128)), (3, (6, 4, 128)),
                                      (4, (2, 2, 64)), (2, (2, 1, 64)), (3, (3, 2, 64)),
                                      (5, (5, 3, 32)), (3, (4, 7, 96)), (4, (3, 2, 160)),
-                                     (2, (9, 1, 32))])
+                                     (2, (9, 1, 32)),
+                                     # chunk tiles: x-y planes of whole 64-cell waves,
+                                     # rows longer than 64 crossing wave boundaries
+                                     (3, (3, 2, 96)), (5, (2, 64, 65)), (4, (5, 1, 128)),
+                                     (3, (1, 64, 67)), (7, (6, 4, 160))])
 def test_small_and_ragged_fp64(N, shape):
     """Tiny, degenerate (n_d = 1, a single cell) and ragged grids whose cell
     counts are not multiples of the 64-lane wave or the 256-thread block."""

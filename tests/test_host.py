@@ -128,3 +128,50 @@ def test_calls_without_context():
 def test_paper_nnz_counts_from_library():
     for N, total in ((3, 70), (7, 438), (39, 14902)):
         assert pm.pm_flux_nnz(N) == total
+
+
+@pytest.mark.parametrize("N,shape", [(3, (4, 5, 6)), (7, (3, 2, 5)), (1, (1, 3, 2)), (39, (2, 3, 4))])
+@pytest.mark.parametrize("parity", [0, 1])
+def test_halo_face_map(N, shape, parity):
+    """Halo faces of a sweep of `parity` when the box is one GPU's share of a
+    split grid.  The sweep reads a dual moment j (l of parity 1 - parity) at
+    c + e_d when j is even under the reflection of d (unstaggered in d), at
+    c - e_d otherwise; so the -d neighbour needs layer 0 of the unstaggered
+    dual moments and the +d neighbour the last layer of the staggered ones.
+    The packed order (faces x-, x+, y-, y+, z-, z+; moments by storage slot;
+    face cells in memory order) is rebuilt here from the oracle's evaluated
+    reflection parities and must equal the library's map element for
+    element; every dual moment sits in exactly one of the two faces of each
+    direction (half of the moments per face pair)."""
+    nz, ny, nx = shape
+    o = basis.reflection_parities(N)
+    V = basis.n_moments(N)
+    deg = np.floor(np.sqrt(np.arange(V))).astype(int)
+    dual = [i for i in range(V) if deg[i] % 2 == 1 - parity]
+    slot = {i: pm.pm_moment_slot(N, i) for i in range(V)}
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    cells = (x + nx * (y + ny * z)).reshape(-1)
+    coord = [x.reshape(-1), y.reshape(-1), z.reshape(-1)]
+    n = (nx, ny, nz)
+    want_m, want_c = [], []
+    for d in range(3):
+        for side in (0, 1):
+            layer = n[d] - 1 if side else 0
+            face = cells[coord[d] == layer]        # memory order of the two other coordinates
+            moms = sorted((i for i in dual if o[i][d] == side), key=lambda i: slot[i])
+            for i in moms:
+                want_m.extend([i] * face.size)
+                want_c.extend(face.tolist())
+        per_dir = [i for i in dual if o[i][d] == 0] + [i for i in dual if o[i][d] == 1]
+        assert sorted(per_dir) == dual
+    cnt, mom, cell = pm.pm_halo_plan(N, nx, ny, nz, parity, with_index=True)
+    assert cnt == len(want_m)
+    assert np.array_equal(mom, np.array(want_m)) and np.array_equal(cell, np.array(want_c))
+    assert pm.pm_halo_plan(N, nx, ny, nz, parity) == cnt
+
+
+def test_halo_plan_validation():
+    for args in ((-1, 2, 2, 2, 0), (3, 0, 2, 2, 0), (3, 2, 2, 2, 2)):
+        with pytest.raises(pm.PmError):
+            pm.pm_halo_plan(*args)
+    assert pm.lib().pm_halo_pack(0, None) == pm.PM_ESTATE
