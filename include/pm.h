@@ -175,6 +175,21 @@ int pm_total(double* sum_u0);
  * non-finite values.  Returns PM_ENONFINITE when that number is not zero. */
 int pm_check(double* max_abs, long long* n_nonfinite);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight stepping loops, harnesses that forbid hipMalloc): pm_check
+ * without allocation or host synchronisation.  The per-block partial
+ * results live in the library's static device scratch (room for 1024
+ * partials per GPU, held until the process ends; this call uses 256, for
+ * any grid size: the reduction strides over the state).  Writes the float64
+ * maximum of |u| over all moments and cells to *dev_max_abs and the number
+ * of non-finite values (unsigned 64-bit) to *dev_nonfinite, both device
+ * pointers owned by the caller, queued on the bound stream with kernels
+ * only (no memset, no allocation, no copy), so it can be captured into a
+ * HIP graph.  Every call on a GPU shares that GPU's scratch: calls that
+ * overlap on one GPU (other streams, other threads) race.  Errors:
+ * PM_ESTATE (no context), PM_EINVAL (NULL output), PM_EDEVICE. */
+int pm_check_noalloc(void* dev_max_abs, void* dev_nonfinite);
+
 /* Queue all further work on this hipStream_t (NULL: the library's own
  * stream).  The stream must outlive the context or the next bind. */
 int pm_bind_stream(void* hip_stream);

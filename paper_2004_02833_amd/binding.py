@@ -20,7 +20,7 @@ PM_N_MAX = 63
 EXPORTED = ("pm_set_precision", "pm_set_scattering", "pm_init", "pm_init_cells", "pm_write", "pm_write_dev", "pm_step", "pm_set_merge",
             "pm_read",
             "pm_read_dev", "pm_set_checkpoint", "pm_grad", "pm_grad_dev", "pm_recording_id",
-            "pm_total", "pm_check",
+            "pm_total", "pm_check", "pm_check_noalloc",
             "pm_bind_stream", "pm_sync", "pm_cfl_warning", "pm_timing", "pm_sweep_times",
             "pm_finalize", "pm_last_error", "pm_flux_nnz", "pm_flux_entries", "pm_moment_grid",
             "pm_moment_slot", "pm_halo_plan", "pm_halo_pack", "pm_halo_unpack", "pm_device_bytes")
@@ -65,6 +65,7 @@ def lib():
             "pm_recording_id": ([], i64),
             "pm_total": ([P(f64)], i32),
             "pm_check": ([P(f64), P(i64)], i32),
+            "pm_check_noalloc": ([vp, vp], i32),
             "pm_bind_stream": ([vp], i32),
             "pm_sync": ([], i32),
             "pm_cfl_warning": ([], i32),
@@ -238,6 +239,13 @@ def pm_check():
     if rc < 0 and rc != PM_ENONFINITE:
         _check(rc)
     return m.value, k.value
+
+
+def pm_check_noalloc(dev_max_abs_ptr, dev_nonfinite_ptr):
+    """pm_check into device memory (float64 max |u|, uint64 count) without
+    allocation or synchronisation."""
+    return _check(lib().pm_check_noalloc(ctypes.c_void_p(int(dev_max_abs_ptr)),
+                                         ctypes.c_void_p(int(dev_nonfinite_ptr))))
 
 
 def pm_bind_stream(stream_ptr):

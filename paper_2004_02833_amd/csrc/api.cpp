@@ -816,6 +816,25 @@ int pm_check(double* max_abs, long long* n_nonfinite) {
     return PM_OK;
 }
 
+int pm_check_noalloc(void* dev_max_abs, void* dev_nonfinite) {
+    if (!C.live) return fail(PM_ESTATE, "no context: call pm_init first");
+    if (!dev_max_abs || !dev_nonfinite) return fail(PM_EINVAL, "output pointers must not be NULL");
+    const int npart = C.npart;
+    if (npart > pm::scratch_partials())
+        return fail(PM_EINVAL, "pm_check_noalloc: " + std::to_string(npart) + " partial results exceed the " +
+                                   std::to_string(pm::scratch_partials()) + " of the static scratch");
+    // the scratch's device address: looked up on the first call on a device
+    // (hipGetSymbolAddress, return code checked), kept per device
+    void* scr = nullptr;
+    HIPCHK(pm::scratch_device(&scr));
+    double* pmax = (double*)scr;
+    unsigned long long* pcnt = (unsigned long long*)((char*)scr + sizeof(double) * pm::scratch_partials());
+    // every partial is written before it is read: nothing to clear
+    HIPCHK(pm::launch_check(C.prec, C.u, C.V, C.g, pmax, pcnt, npart, (double*)dev_max_abs,
+                            (unsigned long long*)dev_nonfinite, C.stream()));
+    return PM_OK;
+}
+
 int pm_bind_stream(void* stream) {
     g_bound = (hipStream_t)stream;
     return PM_OK;

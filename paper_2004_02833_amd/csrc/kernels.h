@@ -125,6 +125,13 @@ hipError_t launch_grad_final(const double* grad, const double* tab, const double
 
 hipError_t launch_fill_zero(void* p, long long bytes, hipStream_t st);
 
+// Device address of the library's static scratch array on the current
+// device (taken once per device with hipGetSymbolAddress), and the number of
+// reduction partials it holds (that many doubles, then that many unsigned
+// long longs).
+hipError_t scratch_device(void** ptr);
+int scratch_partials();
+
 // Halo faces of a sweep, in packing order x-, x+, y-, y+, z-, z+: face f
 // holds the layer `layer[f]` of the moments whose slots are
 // slots[slot0[f] ...] (area[f] cells each); end[f] = packed elements of
