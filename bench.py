@@ -290,14 +290,14 @@ def halo_timing(pm, N=39, prec_name="fp32", steps=5):
     pm_halo_unpack from it; no transfer, one GPU) timed beside the sweeps of
     that share.  Two splits: 2 x 2 x 2 (80^3 sub-boxes, x faces included:
     one 4-byte value per 128-byte line there) and 1 x 2 x 4 (160 x 80 x 40:
-    whole x rows, only y and z faces)."""
+    whole x rows, only y and z faces are exchanged)."""
     import torch
     import workloads
     PREC = {"fp64": (pm.PM_FP64, torch.float64, 8), "fp32": (pm.PM_FP32, torch.float32, 4)}
     prec, tdt, esz = PREC[prec_name]
     dev = torch.device("cuda", 0)
     out = {"moments": "P%d" % N, "dtype": prec_name, "unit": "ms"}
-    for name, (nx, ny, nz) in (("split_2x2x2", (80, 80, 80)), ("split_1x2x4", (160, 80, 40))):
+    for name, (nx, ny, nz), dirs in (("split_2x2x2", (80, 80, 80), 7), ("split_1x2x4", (160, 80, 40), 6)):
         rng = np.random.default_rng(1)
         shape = (nz, ny, nx)
         sa = 0.1 + 0.4 * rng.uniform(size=shape)
@@ -317,20 +317,21 @@ def halo_timing(pm, N=39, prec_name="fp32", steps=5):
             t = pm.pm_sweep_times()
             pm.pm_timing(0)
             sweep_ms = (t["odd"][1] / t["odd"][0] + t["even"][1] / t["even"][0])
-            res = {"cells": nx * ny * nz, "shape_xyz": [nx, ny, nz]}
+            res = {"cells": nx * ny * nz, "shape_xyz": [nx, ny, nz],
+                   "faces": "".join(a for d, a in enumerate("xyz") if (dirs >> d) & 1)}
             tot = 0.0
             for parity in (1, 0):
-                n = pm.pm_halo_plan(N, nx, ny, nz, parity)
+                n = pm.pm_halo_plan(N, nx, ny, nz, parity, dirs)
                 stage = torch.empty(n, dtype=tdt, device=dev)
                 ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
-                pm.pm_halo_pack(parity, stage.data_ptr())       # warm
-                pm.pm_halo_unpack(parity, stage.data_ptr())
+                pm.pm_halo_pack(parity, stage.data_ptr(), dirs)       # warm
+                pm.pm_halo_unpack(parity, stage.data_ptr(), dirs)
                 ev[0].record()
                 for _ in range(steps):
-                    pm.pm_halo_pack(parity, stage.data_ptr())
+                    pm.pm_halo_pack(parity, stage.data_ptr(), dirs)
                 ev[1].record()
                 for _ in range(steps):
-                    pm.pm_halo_unpack(parity, stage.data_ptr())
+                    pm.pm_halo_unpack(parity, stage.data_ptr(), dirs)
                 ev[2].record()
                 torch.cuda.synchronize()
                 pk = ev[0].elapsed_time(ev[1]) / steps

@@ -242,27 +242,32 @@ int pm_moment_slot(int N, int moment);
  * half of the moments on each face (Sec. 3.2 exchanges all of them): the
  * -d neighbour needs this box's layer 0 of the dual moments unstaggered in
  * d (face d-), the +d neighbour its last layer of those staggered in d
- * (face d+).  The packed order is faces x-, x+, y-, y+, z-, z+; within a
- * face the moments by storage slot (pm_moment_slot), then the face cells
- * with the two other coordinates in memory order (x fastest).
+ * (face d+).  `dirs` selects the directions the box is split in (bit 0:
+ * x, bit 1: y, bit 2: z; 1..7): only their faces are packed.  The packed
+ * order is faces x-, x+, y-, y+, z-, z+ (those selected); within a face the
+ * moments by storage slot (pm_moment_slot), then the face cells with the two
+ * other coordinates in memory order (x fastest).  With x fastest in memory
+ * an x face holds one value per row, so splitting only y and z (dirs = 6)
+ * keeps every face access a contiguous row or plane.
  *
  * Host query, no device needed: the number of packed elements for order N,
- * an nx x ny x nz box and a sweep of `parity`; when moment or cell is not
- * NULL, element k's canonical moment and cell x + nx*(y + ny*z) are written
- * for k < cap.  Returns the count, or PM_EINVAL. */
-long long pm_halo_plan(int N, int nx, int ny, int nz, int parity, long long* moment,
+ * an nx x ny x nz box, a sweep of `parity` and the split directions `dirs`;
+ * when moment or cell is not NULL, element k's canonical moment and cell
+ * x + nx*(y + ny*z) are written for k < cap.  Returns the count, or
+ * PM_EINVAL. */
+long long pm_halo_plan(int N, int nx, int ny, int nz, int parity, int dirs, long long* moment,
                        long long* cell, long long cap);
 
-/* Gather the halo faces of the live context's state for a sweep of
- * `parity` into a device buffer of pm_halo_plan(...) elements of the storage
- * type (8, 4 or 2 bytes each), queued on the bound stream.  The caller owns
- * the buffer.  Errors: PM_ESTATE, PM_EINVAL. */
-int pm_halo_pack(int parity, void* device_buf);
+/* Gather the halo faces (directions `dirs`) of the live context's state for
+ * a sweep of `parity` into a device buffer of pm_halo_plan(...) elements of
+ * the storage type (8, 4 or 2 bytes each), queued on the bound stream.  The
+ * caller owns the buffer.  Errors: PM_ESTATE, PM_EINVAL. */
+int pm_halo_pack(int parity, int dirs, void* device_buf);
 
 /* The inverse scatter: write the packed elements into the same moments and
  * cells of the state (where a neighbouring GPU's faces would land in its
  * ghost layers).  Queued on the bound stream.  Errors: PM_ESTATE, PM_EINVAL. */
-int pm_halo_unpack(int parity, const void* device_buf);
+int pm_halo_unpack(int parity, int dirs, const void* device_buf);
 
 /* Bytes of device memory the context holds (0 without a context). */
 long long pm_device_bytes(void);

@@ -77,9 +77,9 @@ def lib():
             "pm_flux_entries": ([i32, P(i32), P(i32), P(i32), P(f64), i32], i32),
             "pm_moment_grid": ([i32, i32], i32),
             "pm_moment_slot": ([i32, i32], i32),
-            "pm_halo_plan": ([i32, i32, i32, i32, i32, P(i64), P(i64), i64], i64),
-            "pm_halo_pack": ([i32, vp], i32),
-            "pm_halo_unpack": ([i32, vp], i32),
+            "pm_halo_plan": ([i32, i32, i32, i32, i32, i32, P(i64), P(i64), i64], i64),
+            "pm_halo_pack": ([i32, i32, vp], i32),
+            "pm_halo_unpack": ([i32, i32, vp], i32),
             "pm_device_bytes": ([], i64),
         }
         for name, (args, res) in sig.items():
@@ -304,25 +304,27 @@ def pm_moment_slot(N, moment):
     return _check(lib().pm_moment_slot(int(N), int(moment)))
 
 
-def pm_halo_plan(N, nx, ny, nz, parity, with_index=False):
-    """Count of packed halo elements for a sweep of `parity`; with_index:
+def pm_halo_plan(N, nx, ny, nz, parity, dirs=7, with_index=False):
+    """Count of packed halo elements for a sweep of `parity` with the box
+    split in the directions of `dirs` (bits x = 1, y = 2, z = 4); with_index:
     (count, moment array, cell array) in the packed order."""
-    n = _check(lib().pm_halo_plan(int(N), int(nx), int(ny), int(nz), int(parity), None, None, 0))
+    a = (int(N), int(nx), int(ny), int(nz), int(parity), int(dirs))
+    n = _check(lib().pm_halo_plan(*a, None, None, 0))
     if not with_index:
         return n
     mom = np.empty(n, np.int64)
     cell = np.empty(n, np.int64)
-    P = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_longlong))
-    _check(lib().pm_halo_plan(int(N), int(nx), int(ny), int(nz), int(parity), P(mom), P(cell), n))
+    P = lambda x: x.ctypes.data_as(ctypes.POINTER(ctypes.c_longlong))
+    _check(lib().pm_halo_plan(*a, P(mom), P(cell), n))
     return n, mom, cell
 
 
-def pm_halo_pack(parity, device_ptr):
-    return _check(lib().pm_halo_pack(int(parity), ctypes.c_void_p(int(device_ptr))))
+def pm_halo_pack(parity, device_ptr, dirs=7):
+    return _check(lib().pm_halo_pack(int(parity), int(dirs), ctypes.c_void_p(int(device_ptr))))
 
 
-def pm_halo_unpack(parity, device_ptr):
-    return _check(lib().pm_halo_unpack(int(parity), ctypes.c_void_p(int(device_ptr))))
+def pm_halo_unpack(parity, device_ptr, dirs=7):
+    return _check(lib().pm_halo_unpack(int(parity), int(dirs), ctypes.c_void_p(int(device_ptr))))
 
 
 def pm_device_bytes():

@@ -15,7 +15,7 @@ ARCH = "gfx950"
 DEVFLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 COMMON = ["-O3", "-fPIC", "-std=c++17", "--offload-arch=" + ARCH, "-Wall",
           "-Wno-unused-result", "-I" + os.path.join(HERE, "..", "include")]
-SOURCES = [("api.cpp", False), ("flux.cpp", False), ("kernels.hip", True)]
+SOURCES = [("api.cpp", False), ("flux.cpp", False), ("kernels.hip", True), ("scratch.hip", True)]
 
 
 def build(verbose=False):

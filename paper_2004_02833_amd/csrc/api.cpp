@@ -375,7 +375,21 @@ HaloPlan halo_plan(const pm::Layout& L, int nx, int ny, int nz, int parity) {
         end += cnt * hp.hf.area[f];
         hp.hf.end[f] = end;
     }
+    hp.hf.slot0[6] = (int)hp.slots.size();
     return hp;
+}
+
+// The faces of the directions in `dirs` (bit d: direction d split across
+// GPUs): the others get no cells, and the packed offsets close up.
+pm::HaloFaces halo_masked(pm::HaloFaces hf, int dirs) {
+    long long end = 0;
+    for (int f = 0; f < 6; ++f) {
+        const long long cnt = hf.slot0[f + 1] - hf.slot0[f];
+        if (!((dirs >> (f >> 1)) & 1)) hf.area[f] = 0;
+        end += cnt * hf.area[f];
+        hf.end[f] = end;
+    }
+    return hf;
 }
 
 int check_moment(int moment) {
@@ -915,21 +929,23 @@ int pm_moment_slot(int N, int moment) {
     return pm::make_layout(N).slot_of[moment];
 }
 
-long long pm_halo_plan(int N, int nx, int ny, int nz, int parity, long long* moment,
+long long pm_halo_plan(int N, int nx, int ny, int nz, int parity, int dirs, long long* moment,
                        long long* cell, long long cap) {
     if (N < 0 || N > PM_N_MAX) return fail(PM_EINVAL, "N must be in [0, 63]");
     if (nx < 1 || ny < 1 || nz < 1) return fail(PM_EINVAL, "grid sizes must be >= 1");
     if (parity != 0 && parity != 1) return fail(PM_EINVAL, "parity must be 0 or 1");
+    if (dirs < 1 || dirs > 7) return fail(PM_EINVAL, "dirs must be a nonzero mask of bits 1 (x), 2 (y), 4 (z)");
     if (cap < 0) return fail(PM_EINVAL, "cap < 0");
     const pm::Layout L = pm::make_layout(N);
-    const HaloPlan hp = halo_plan(L, nx, ny, nz, parity);
+    HaloPlan hp = halo_plan(L, nx, ny, nz, parity);
+    hp.hf = halo_masked(hp.hf, dirs);
     const long long total = hp.hf.end[5];
     if (moment || cell) {
         long long k = 0;
         for (int f = 0; f < 6 && k < cap; ++f) {
+            if (hp.hf.area[f] == 0) continue;
             const int d = f >> 1, layer = hp.hf.layer[f];
-            const long long cnt = f < 5 ? hp.hf.slot0[f + 1] - hp.hf.slot0[f]
-                                        : (long long)hp.slots.size() - hp.hf.slot0[f];
+            const long long cnt = hp.hf.slot0[f + 1] - hp.hf.slot0[f];
             for (long long j = 0; j < cnt && k < cap; ++j)
                 for (long long a = 0; a < hp.hf.area[f] && k < cap; ++a, ++k) {
                     long long c;
@@ -949,21 +965,24 @@ long long pm_halo_plan(int N, int nx, int ny, int nz, int parity, long long* mom
 
 namespace {
 
-int halo_move(int parity, void* buf, bool unpack) {
+int halo_move(int parity, int dirs, void* buf, bool unpack) {
     if (!C.live) return fail(PM_ESTATE, "no context: call pm_init first");
     if (parity != 0 && parity != 1) return fail(PM_EINVAL, "parity must be 0 or 1");
+    if (dirs < 1 || dirs > 7) return fail(PM_EINVAL, "dirs must be a nonzero mask of bits 1 (x), 2 (y), 4 (z)");
     if (!buf) return fail(PM_EINVAL, "buffer is NULL");
-    const HaloPlan& hp = C.halo[parity];
-    HIPCHK(pm::launch_halo(C.prec, unpack, C.u, buf, C.halo_slots[parity], hp.hf, C.g, C.stream()));
+    const pm::HaloFaces hf = halo_masked(C.halo[parity].hf, dirs);
+    HIPCHK(pm::launch_halo(C.prec, unpack, C.u, buf, C.halo_slots[parity], hf, C.g, C.stream()));
     return PM_OK;
 }
 
 }  // namespace
 
-int pm_halo_pack(int parity, void* device_buf) { return halo_move(parity, device_buf, false); }
+int pm_halo_pack(int parity, int dirs, void* device_buf) {
+    return halo_move(parity, dirs, device_buf, false);
+}
 
-int pm_halo_unpack(int parity, const void* device_buf) {
-    return halo_move(parity, const_cast<void*>(device_buf), true);
+int pm_halo_unpack(int parity, int dirs, const void* device_buf) {
+    return halo_move(parity, dirs, const_cast<void*>(device_buf), true);
 }
 
 long long pm_device_bytes(void) {

@@ -134,13 +134,13 @@ int scratch_partials();
 
 // Halo faces of a sweep, in packing order x-, x+, y-, y+, z-, z+: face f
 // holds the layer `layer[f]` of the moments whose slots are
-// slots[slot0[f] ...] (area[f] cells each); end[f] = packed elements of
-// faces 0..f.
+// slots[slot0[f] .. slot0[f + 1]) (area[f] cells each; slot0[6] = all
+// moments); end[f] = packed elements of faces 0..f.
 struct HaloFaces {
     long long end[6];
     long long area[6];
     int layer[6];
-    int slot0[6];
+    int slot0[7];
 };
 hipError_t launch_halo(int prec, bool unpack, void* u, void* buf, const int* slots, HaloFaces hf,
                        GridDesc g, hipStream_t st);

@@ -48,7 +48,7 @@
 #define PM_WIN_K16 3
 #endif
 #ifndef PM_WIN_K64R
-#define PM_WIN_K64R 3   // FP64 where waves do not hold whole rows
+#define PM_WIN_K64R 3   // FP64 where waves do not hold whole rows (P39 160^3: 20.28 vs 20.88 ms at K = 2)
 #endif
 
 namespace pm {
@@ -534,17 +534,18 @@ __device__ __forceinline__ long long tile_cell(const TileMap& m, long long tile,
         return c;
     }
     if (m.sw < 0) {
-        // chunk tiles: chunk k of 64 cells of an x-y plane, waves stacked in
-        // z; a wave past the grid takes the last plane and lanes past the
-        // plane's last cell take that cell (valid addresses, not stored)
+        // chunk tiles: chunk k of 64 CPL cells of an x-y plane, waves
+        // stacked in z; a wave past the grid takes the last plane and lanes
+        // past the plane's last cell take its last CPL cells (valid
+        // addresses, not stored; nx is a multiple of CPL)
         const long long nxy = (long long)g.nx * g.ny;
         const long long k = tile % m.nty;
         const int zt = (int)(tile / m.nty);
         int z = zt * (TPB / 64) + (tid >> 6);
-        long long p = k * 64 + (tid & 63);
+        long long p = (k * 64 + (tid & 63)) * CPL;
         live = z < g.nz && p < nxy;
         if (z >= g.nz) z = g.nz - 1;
-        if (p >= nxy) p = nxy - 1;
+        if (p >= nxy) p = nxy - CPL;
         return (long long)z * nxy + p;
     }
     const int ls = m.sw / CPL;  // lanes per segment row
@@ -623,6 +624,10 @@ template <> struct MinWaves<float> { static constexpr int v = PM_WPE32; };
 #endif
 #ifndef PM_CHUNK_RAGGED
 #define PM_CHUNK_RAGGED 1
+#endif
+// chunk tiles also for two cells per lane (BF16: chunks of 128 cells)
+#ifndef PM_CHUNK_TILES2
+#define PM_CHUNK_TILES2 1
 #endif
 // resident waves asked for the FP64 forward sweeps with loaded x neighbours
 #ifndef PM_WPE64N
@@ -1054,16 +1059,17 @@ static void launch_win_t(T* pool, StateOffs so, double* gp, const double* tab, c
                            an.gl, an.tau, rowbase, a.N, a.parity, a.npass, per_xcd, ntile, tm, g);
         return;
     }
-    if constexpr (CPL == 1) {
+    {
         // rows of nx > 64 cells whose x-y planes hold whole waves: chunk
-        // tiles, waves stacked in z
+        // tiles of 64 CPL cells, waves stacked in z
         const long long nxy = (long long)g.nx * g.ny;
-        if (PM_CHUNK_TILES && g.nx > 64 && (nxy % 64 == 0 || (PM_CHUNK_RAGGED && sw == 0))) {
+        if (PM_CHUNK_TILES && (CPL == 1 || PM_CHUNK_TILES2) && g.nx > 64 && g.nx % CPL == 0 &&
+            (nxy % (64 * CPL) == 0 || (PM_CHUNK_RAGGED && sw == 0))) {
             // grouped passes and tile blocks: measured on P39 at 160^3
             // (FP64 -3.6%, FP32 -9.2% sweep time with both); whole-row waves
             // keep pass-major order, where grouping was slower (64^3: +1.4%
             // FP64 with groups of 3)
-            TileMap tc{-1, 1, (int)((nxy + 63) / 64), (g.nz + TPB / 64 - 1) / (TPB / 64),
+            TileMap tc{-1, 1, (int)((nxy + 64 * CPL - 1) / (64 * CPL)), (g.nz + TPB / 64 - 1) / (TPB / 64),
                        PM_CHUNK_PASS_GROUP, PM_CHUNK_GY, PM_CHUNK_GZ};
             const long long nt = (long long)tc.nty * tc.ntz;
             const int px = (int)((nt + kXcds - 1) / kXcds);
@@ -1404,42 +1410,67 @@ namespace pm {
 
 // ------------------------------------------------------------- halo faces --
 // Gather (pack) or scatter (unpack) of the one-cell halo faces a sweep of
-// one parity needs from its neighbours when the box is split across GPUs:
-// element k of the packed buffer lies in face f (the first face whose end
-// exceeds k), moment j = (k - start) / area of that face (slot slots[...]),
-// face cell (k - start) mod area, the two other coordinates in memory order.
+// one parity needs from its neighbours when the box is split across GPUs.
+// Workgroup (x, y) takes chunk y of kHaloChunk packed elements of the
+// (face, moment) pair x; a lane moves kHaloPer elements of the chunk, all
+// loads issued before the stores.  Inside a face the elements follow memory
+// order (fast coordinate: y for an x face, x for y and z faces), so lanes
+// touch consecutive packed elements and, for y and z faces, consecutive
+// cells.  Packed element end[f-1] + j area[f] + a, as the face map lists it.
+constexpr int kHaloPer = 8;
+constexpr int kHaloChunk = 256 * kHaloPer;
+
 template <class T, bool UNPACK>
-__global__ void k_halo(T* __restrict__ u, T* __restrict__ buf, const int* __restrict__ slots,
-                       HaloFaces hf, GridDesc g) {
-    const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= hf.end[5]) return;
+__global__ void __launch_bounds__(256)
+k_halo(T* __restrict__ u, T* __restrict__ buf, const int* __restrict__ slots, HaloFaces hf,
+       GridDesc g) {
+    const int fm = blockIdx.x;  // (face, moment) pair
     int f = 0;
 #pragma unroll
-    for (int i = 0; i < 5; ++i) f += k >= hf.end[i] ? 1 : 0;
-    const long long start = f == 0 ? 0 : hf.end[f - 1];
-    const long long area = hf.area[f];
-    const long long r = k - start;
-    const long long j = r / area, a = r - j * area;
+    for (int i = 0; i < 5; ++i) f += fm >= hf.slot0[i + 1] ? 1 : 0;
+    const int area = (int)hf.area[f];
+    const int a0 = blockIdx.y * kHaloChunk + threadIdx.x;
+    if (a0 >= area) return;
+    const int j = fm - hf.slot0[f];
     const int d = f >> 1, layer = hf.layer[f];
-    long long c;
-    if (d == 0)
-        c = layer + (long long)g.nx * a;                      // a = y + ny z
-    else if (d == 1)
-        c = (a % g.nx) + (long long)g.nx * (layer + (long long)g.ny * (a / g.nx));  // a = x + nx z
-    else
-        c = a + (long long)g.nx * g.ny * layer;               // a = x + nx y
-    T* p = u + (long long)slots[hf.slot0[f] + j] * g.pstride + c;
-    if (UNPACK)
-        *p = buf[k];
-    else
-        buf[k] = *p;
+    const int nfast = d == 0 ? g.ny : g.nx;
+    const long long start = (f == 0 ? 0 : hf.end[f - 1]) + (long long)j * area;
+    T* plane = u + (long long)slots[fm] * g.pstride;
+    long long cell[kHaloPer];
+    T v[kHaloPer];
+#pragma unroll
+    for (int i = 0; i < kHaloPer; ++i) {
+        const int a = a0 + i * 256;
+        const int slow = a / nfast, fast = a - slow * nfast;
+        if (d == 0)
+            cell[i] = layer + (long long)g.nx * (fast + (long long)g.ny * slow);
+        else if (d == 1)
+            cell[i] = fast + (long long)g.nx * (layer + (long long)g.ny * slow);
+        else
+            cell[i] = fast + (long long)g.nx * (slow + (long long)g.ny * layer);
+        if (a < area) v[i] = UNPACK ? buf[start + a] : plane[cell[i]];
+    }
+#pragma unroll
+    for (int i = 0; i < kHaloPer; ++i) {
+        const int a = a0 + i * 256;
+        if (a >= area) break;
+        if (UNPACK)
+            plane[cell[i]] = v[i];
+        else
+            buf[start + a] = v[i];
+    }
 }
 
 hipError_t launch_halo(int prec, bool unpack, void* u, void* buf, const int* slots, HaloFaces hf,
                        GridDesc g, hipStream_t st) {
-    const long long n = hf.end[5];
-    if (n <= 0) return hipSuccess;
-    const dim3 grid((unsigned)((n + 255) / 256)), block(256);
+    const int nfm = hf.slot0[6];
+    if (nfm <= 0 || hf.end[5] <= 0) return hipSuccess;
+    long long amax = 0;
+    for (int f = 0; f < 6; ++f) amax = hf.area[f] > amax ? hf.area[f] : amax;
+    if (amax >= (1LL << 31) - kHaloChunk || nfm > (1 << 30)) return hipErrorInvalidValue;
+    const long long ny = (amax + kHaloChunk - 1) / kHaloChunk;
+    if (ny > 65535) return hipErrorInvalidValue;  // grid y limit
+    const dim3 grid((unsigned)nfm, (unsigned)ny), block(256);
 #define PM_HALO(T)                                                                               \
     if (unpack)                                                                                  \
         hipLaunchKernelGGL((k_halo<T, true>), grid, block, 0, st, (T*)u, (T*)buf, slots, hf, g); \
@@ -1455,38 +1486,5 @@ hipError_t launch_halo(int prec, bool unpack, void* u, void* buf, const int* slo
 #undef PM_HALO
     return hipGetLastError();
 }
-
-}  // namespace pm
-
-namespace pm {
-
-// ---------------------------------------------------- static scratch memory --
-// Partial results of pm_check_noalloc: kScratchPartials maxima (double) and
-// as many counts (unsigned long long).  Each GPU the library runs on holds
-// its own copy until the process ends.  Host code never uses the array's
-// name as an address: scratch_device() takes the device address from
-// hipGetSymbolAddress once per device and keeps it.
-constexpr int kScratchPartials = 1024;
-static __device__ __align__(256) unsigned char scratch[kScratchPartials * (sizeof(double) + sizeof(unsigned long long))];
-
-constexpr int kMaxDevices = 64;
-
-hipError_t scratch_device(void** ptr) {
-    static void* addr[kMaxDevices] = {nullptr};
-    int dev = 0;
-    hipError_t e = hipGetDevice(&dev);
-    if (e != hipSuccess) return e;
-    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
-    if (!addr[dev]) {
-        void* p = nullptr;
-        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
-        if (e != hipSuccess) return e;
-        addr[dev] = p;
-    }
-    *ptr = addr[dev];
-    return hipSuccess;
-}
-
-int scratch_partials() { return kScratchPartials; }
 
 }  // namespace pm

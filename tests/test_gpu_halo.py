@@ -32,22 +32,22 @@ def test_halo_pack_unpack(N, shape, prec):
         pm.pm_bind_stream(torch.cuda.current_stream(dev).cuda_stream)
         for i in range(V):
             pm.pm_write(i, rng.normal(size=shape))
-        for parity in (0, 1):
-            n, mom, cell = pm.pm_halo_plan(N, nx, ny, nz, parity, with_index=True)
+        for parity, dirs in ((0, 7), (1, 7), (1, 6), (0, 5)):
+            n, mom, cell = pm.pm_halo_plan(N, nx, ny, nz, parity, dirs, with_index=True)
             state = read_all(V, shape)
             buf = torch.empty(n, dtype=TDT[prec], device=dev)
-            pm.pm_halo_pack(parity, buf.data_ptr())
+            pm.pm_halo_pack(parity, buf.data_ptr(), dirs)
             got = buf.double().cpu().numpy()
             assert np.array_equal(got, state[mom, cell])
             # unpack a changed buffer: exactly the face elements change
             new = (-2.0 * buf.double() + 1.0).to(TDT[prec])
-            pm.pm_halo_unpack(parity, new.data_ptr())
+            pm.pm_halo_unpack(parity, new.data_ptr(), dirs)
             after = read_all(V, shape)
             want = state.copy()
             want[mom, cell] = new.double().cpu().numpy()
             assert np.array_equal(after, want)
             # and the original buffer restores the state bit for bit
-            pm.pm_halo_unpack(parity, buf.data_ptr())
+            pm.pm_halo_unpack(parity, buf.data_ptr(), dirs)
             assert np.array_equal(read_all(V, shape), state)
     finally:
         pm.pm_finalize()

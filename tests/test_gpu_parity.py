@@ -233,7 +233,9 @@ def test_merged_schedule(shape):
     assert relerr(out[(1, 0)], out[(0, 0)]) <= 1e-14
 
 
-@pytest.mark.parametrize("shape", [(4, 6, 64), (3, 5, 12), (2, 3, 7), (3, 2, 160)])
+@pytest.mark.parametrize("shape", [(4, 6, 64), (3, 5, 12), (2, 3, 7), (3, 2, 160),
+                                   # chunk tiles of 128 cells for BF16 (whole and ragged planes)
+                                   (4, 4, 160), (3, 5, 100), (2, 3, 500)])
 def test_bf16_and_fp32_small_shapes(shape):
     """BF16 storage (two cells per lane where rows have an even length, one
     otherwise) and FP32 against the FP64 oracle on small grids."""

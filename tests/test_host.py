@@ -132,7 +132,8 @@ def test_paper_nnz_counts_from_library():
 
 @pytest.mark.parametrize("N,shape", [(3, (4, 5, 6)), (7, (3, 2, 5)), (1, (1, 3, 2)), (39, (2, 3, 4))])
 @pytest.mark.parametrize("parity", [0, 1])
-def test_halo_face_map(N, shape, parity):
+@pytest.mark.parametrize("dirs", [7, 6, 1, 4])
+def test_halo_face_map(N, shape, parity, dirs):
     """Halo faces of a sweep of `parity` when the box is one GPU's share of a
     split grid.  The sweep reads a dual moment j (l of parity 1 - parity) at
     c + e_d when j is even under the reflection of d (unstaggered in d), at
@@ -142,7 +143,8 @@ def test_halo_face_map(N, shape, parity):
     face cells in memory order) is rebuilt here from the oracle's evaluated
     reflection parities and must equal the library's map element for
     element; every dual moment sits in exactly one of the two faces of each
-    direction (half of the moments per face pair)."""
+    direction (half of the moments per face pair).  `dirs` selects the split
+    directions whose faces are packed."""
     nz, ny, nx = shape
     o = basis.reflection_parities(N)
     V = basis.n_moments(N)
@@ -156,6 +158,8 @@ def test_halo_face_map(N, shape, parity):
     want_m, want_c = [], []
     for d in range(3):
         for side in (0, 1):
+            if not (dirs >> d) & 1:
+                continue
             layer = n[d] - 1 if side else 0
             face = cells[coord[d] == layer]        # memory order of the two other coordinates
             moms = sorted((i for i in dual if o[i][d] == side), key=lambda i: slot[i])
@@ -164,14 +168,14 @@ def test_halo_face_map(N, shape, parity):
                 want_c.extend(face.tolist())
         per_dir = [i for i in dual if o[i][d] == 0] + [i for i in dual if o[i][d] == 1]
         assert sorted(per_dir) == dual
-    cnt, mom, cell = pm.pm_halo_plan(N, nx, ny, nz, parity, with_index=True)
+    cnt, mom, cell = pm.pm_halo_plan(N, nx, ny, nz, parity, dirs, with_index=True)
     assert cnt == len(want_m)
     assert np.array_equal(mom, np.array(want_m)) and np.array_equal(cell, np.array(want_c))
-    assert pm.pm_halo_plan(N, nx, ny, nz, parity) == cnt
+    assert pm.pm_halo_plan(N, nx, ny, nz, parity, dirs) == cnt
 
 
 def test_halo_plan_validation():
-    for args in ((-1, 2, 2, 2, 0), (3, 0, 2, 2, 0), (3, 2, 2, 2, 2)):
+    for args in ((-1, 2, 2, 2, 0), (3, 0, 2, 2, 0), (3, 2, 2, 2, 2), (3, 2, 2, 2, 0, 0), (3, 2, 2, 2, 0, 8)):
         with pytest.raises(pm.PmError):
             pm.pm_halo_plan(*args)
-    assert pm.lib().pm_halo_pack(0, None) == pm.PM_ESTATE
+    assert pm.lib().pm_halo_pack(0, 7, None) == pm.PM_ESTATE
