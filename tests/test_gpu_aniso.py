@@ -48,7 +48,8 @@ def problem(N, shape, seed):
 
 
 @pytest.mark.parametrize("N,shape", [(1, (3, 4, 5)), (3, (5, 6, 7)), (3, (2, 3, 70)),
-                                     (7, (4, 6, 64)), (7, (3, 5, 12)), (8, (4, 4, 32))])
+                                     (7, (4, 6, 64)), (7, (3, 5, 12)), (8, (4, 4, 32)),
+                                     (5, (3, 4, 160)), (4, (2, 3, 100))])
 def test_small_and_ragged_fp64(N, shape):
     say("case aniso fp64", N, shape)
     rng, sa, ss, q, u = problem(N, shape, 100 + N)
@@ -107,7 +108,7 @@ def test_p39_fp64_fp32_bf16():
         assert e <= tol, prec
 
 
-@pytest.mark.parametrize("shape", [(4, 6, 64), (3, 5, 12), (2, 3, 7)])
+@pytest.mark.parametrize("shape", [(4, 6, 64), (3, 5, 12), (2, 3, 7), (3, 4, 160), (2, 3, 100)])
 def test_fp32_bf16_small_shapes(shape):
     N = 5
     _, sa, ss, q, u = problem(N, shape, 130)
