@@ -62,3 +62,39 @@ def test_source_hash_ignores_comments_not_code(tmp_path, monkeypatch):
     assert bench.kernel_source_hash() != h0
     k.write_text(text)
     assert bench.kernel_source_hash() == h0
+
+
+def test_traffic_summary_scales_and_splits_by_parity(tmp_path):
+    """bench_probe/traffic_summary.py: counters scaled by the copy's known
+    bytes, odd and even launches told apart by their writes, bytes per launch
+    keyed by the source hash bench.py checks."""
+    import json
+    from bench_probe import traffic_summary as ts
+
+    def write(name, counter, vals):
+        d = tmp_path / name
+        d.mkdir()
+        with open(d / "p_counter_collection.csv", "w") as f:
+            f.write("Dispatch_Id,Counter_Name,Counter_Value\n")
+            for i, v in enumerate(vals):
+                f.write("%d,%s,%r\n" % (i, counter, v))
+
+    kib = 4 * 2 ** 30 / 1024
+    write("copy_FETCH_SIZE", "FETCH_SIZE", [kib / 2] * 3)   # reads 2x what FETCH_SIZE shows
+    write("copy_WRITE_SIZE", "WRITE_SIZE", [kib] * 3)
+    ncell = 64 ** 3
+    odd, even = bench.sweep_bytes(39, ncell, 8, 1), bench.sweep_bytes(39, ncell, 8, 0)
+    w_odd, w_even = 820 * 8 * ncell, 780 * 8 * ncell
+    # launches odd, even, odd; fetched bytes 1.2x the algorithmic reads
+    f = [1.2 * (odd - w_odd) / 2048, 1.2 * (even - w_even) / 2048, 1.2 * (odd - w_odd) / 2048]
+    write("p39_smooth_fp64_FETCH_SIZE", "FETCH_SIZE", f)
+    write("p39_smooth_fp64_WRITE_SIZE", "WRITE_SIZE", [w_odd / 1024, w_even / 1024, w_odd / 1024])
+    out = tmp_path / "traffic.json"
+    ts.main(str(tmp_path), str(out))
+    rec = json.load(open(out))
+    assert set(rec) == {"sweep_odd/p39_smooth/f64", "sweep_even/p39_smooth/f64"}
+    assert rec["sweep_odd/p39_smooth/f64"]["source_hash"] == bench.kernel_source_hash()
+    got = rec["sweep_odd/p39_smooth/f64"]["bytes_per_launch"]
+    assert abs(got - (1.2 * (odd - w_odd) + w_odd)) < 16
+    got = rec["sweep_even/p39_smooth/f64"]["bytes_per_launch"]
+    assert abs(got - (1.2 * (even - w_even) + w_even)) < 16
