@@ -1031,6 +1031,14 @@ int adj_depth(int prec) { return prec == kF64 ? PM_ADJ_K64 : prec == kF32 ? PM_A
 #ifndef PM_CPL16
 #define PM_CPL16 2
 #endif
+// FP32 forward sweeps of low orders (N <= PM_ROW2_NMAX) on rows of 128
+// cells: two cells per lane, so that every wave holds a whole row (x
+// neighbours by rotation).  Measured on 128^3, FP32 odd sweep: P7 0.196 vs
+// 0.236 ms, P3 0.061 vs 0.070; slower at P19 (1.255 vs 1.202) and P39
+// (5.07 vs 4.66), and on chunk tiles (P7 160^3 0.468 vs 0.443).
+#ifndef PM_ROW2_NMAX
+#define PM_ROW2_NMAX 10
+#endif
 
 template <class T, int K, int CPL, int MODE, bool ANI>
 static void launch_win_t(T* pool, StateOffs so, double* gp, const double* tab, const float* tabf,
@@ -1111,7 +1119,9 @@ hipError_t launch_sweep_win(int prec, void* pool, StateOffs so, const double* ta
         else
             launch_fwd<double, 3, 1>(pool, so, tab, tabf, rowbase, an, a, g, st);
     } else if (prec == kF32) {
-        if (a.K == 2)
+        if (a.N <= PM_ROW2_NMAX && a.K == 2 && g.nx == 128)
+            launch_fwd<float, 2, 2>(pool, so, tab, tabf, rowbase, an, a, g, st);
+        else if (a.K == 2)
             launch_fwd<float, 2, 1>(pool, so, tab, tabf, rowbase, an, a, g, st);
 #if PM_MAX_K >= 4
         else if (a.K == 4)

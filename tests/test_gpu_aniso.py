@@ -108,7 +108,7 @@ def test_p39_fp64_fp32_bf16():
         assert e <= tol, prec
 
 
-@pytest.mark.parametrize("shape", [(4, 6, 64), (3, 5, 12), (2, 3, 7), (3, 4, 160), (2, 3, 100)])
+@pytest.mark.parametrize("shape", [(4, 6, 64), (3, 5, 12), (2, 3, 7), (3, 4, 160), (2, 3, 100), (3, 4, 128)])
 def test_fp32_bf16_small_shapes(shape):
     N = 5
     _, sa, ss, q, u = problem(N, shape, 130)

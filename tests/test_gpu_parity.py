@@ -235,10 +235,13 @@ def test_merged_schedule(shape):
 
 @pytest.mark.parametrize("shape", [(4, 6, 64), (3, 5, 12), (2, 3, 7), (3, 2, 160),
                                    # chunk tiles of 128 cells for BF16 (whole and ragged planes)
-                                   (4, 4, 160), (3, 5, 100), (2, 3, 500)])
+                                   (4, 4, 160), (3, 5, 100), (2, 3, 500),
+                                   # rows of 128 cells: FP32 at two cells per lane, whole-row waves
+                                   (3, 4, 128), (2, 1, 128)])
 def test_bf16_and_fp32_small_shapes(shape):
     """BF16 storage (two cells per lane where rows have an even length, one
-    otherwise) and FP32 against the FP64 oracle on small grids."""
+    otherwise) and FP32 (two cells per lane on rows of 128 cells at this
+    order) against the FP64 oracle on small grids."""
     N = 5
     sa, ss, q, u = rand_problem(N, shape, 31)
     h, dt = 0.2, 0.07
