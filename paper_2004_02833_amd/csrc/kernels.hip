@@ -33,10 +33,16 @@
 #define PM_ADJ_K32 2
 #endif
 #ifndef PM_WIN_KLOW
-#define PM_WIN_KLOW 2   // FP64 and FP32 at N <= PM_N_LOW
+#define PM_WIN_KLOW 2   // FP64 and FP32 at N <= PM_N_LOW (PM_N_LOW_LONG on rows > 64)
 #endif
 #ifndef PM_N_LOW
 #define PM_N_LOW 20
+#endif
+// on rows longer than 64 cells: P19, FP32 500^3 odd + even sweep 149.9 vs
+// 160.7 ms at depth 3 / 2, FP64 128^3 5.26 vs 5.41 ms, 160^3 10.34 vs 10.67;
+// but P7 and P3 lose 2-24% at depth 3 (P19 FP32 128^3: +4.9%)
+#ifndef PM_N_LOW_LONG
+#define PM_N_LOW_LONG 15
 #endif
 #ifndef PM_WIN_K32
 #define PM_WIN_K32 2
@@ -1013,9 +1019,21 @@ static_assert(PM_ADJ_K64 >= 2 && PM_ADJ_K64 <= 3 && PM_ADJ_K32 >= 2 && PM_ADJ_K3
               "forward FP64 and FP32 sweeps are instantiated for depths 2..PM_MAX_K, "
               "the transposed ones for 2 and 3");
 
+// FP32 forward sweeps of low orders (N <= PM_ROW2_NMAX) on rows of 128
+// cells: two cells per lane, so that every wave holds a whole row (x
+// neighbours by rotation).  Measured on 128^3, FP32 odd sweep: P7 0.196 vs
+// 0.236 ms, P3 0.061 vs 0.070; slower at P19 (1.255 vs 1.202) and P39
+// (5.07 vs 4.66), and on chunk tiles (P7 160^3 0.468 vs 0.443).
+#ifndef PM_ROW2_NMAX
+#define PM_ROW2_NMAX 10
+#endif
+
 int win_depth(int prec, int nx, int N) {
     if (prec == kBF16) return PM_WIN_K16;
-    if (N <= PM_N_LOW) return PM_WIN_KLOW;
+    // rows longer than 64 cells (chunk or segment tiles), except FP32 rows of
+    // 128 cells at two cells per lane, take the deeper passes from a lower N
+    const bool long_rows = nx > 64 && !(prec == kF32 && nx == 128 && N <= PM_ROW2_NMAX);
+    if (N <= (long_rows ? PM_N_LOW_LONG : PM_N_LOW)) return PM_WIN_KLOW;
     if (prec == kF64) return nx == 64 ? PM_WIN_K64 : PM_WIN_K64R;
     return nx == 64 ? PM_WIN_K32 : PM_WIN_K32R;  // FP32: one cell per lane
 }
@@ -1030,14 +1048,6 @@ int adj_depth(int prec) { return prec == kF64 ? PM_ADJ_K64 : prec == kF32 ? PM_A
 // faster in FP64 and slower in FP32.
 #ifndef PM_CPL16
 #define PM_CPL16 2
-#endif
-// FP32 forward sweeps of low orders (N <= PM_ROW2_NMAX) on rows of 128
-// cells: two cells per lane, so that every wave holds a whole row (x
-// neighbours by rotation).  Measured on 128^3, FP32 odd sweep: P7 0.196 vs
-// 0.236 ms, P3 0.061 vs 0.070; slower at P19 (1.255 vs 1.202) and P39
-// (5.07 vs 4.66), and on chunk tiles (P7 160^3 0.468 vs 0.443).
-#ifndef PM_ROW2_NMAX
-#define PM_ROW2_NMAX 10
 #endif
 
 template <class T, int K, int CPL, int MODE, bool ANI>

@@ -307,13 +307,14 @@ def test_long_rows_linear_tiles(shape):
         assert e <= tol, prec
 
 
-@pytest.mark.parametrize("N", [20, 21])
-@pytest.mark.parametrize("shape", [(2, 2, 64), (2, 3, 48)])
+@pytest.mark.parametrize("N,shape", [(20, (2, 2, 64)), (21, (2, 2, 64)), (20, (2, 3, 48)), (21, (2, 3, 48)),
+                                     # rows longer than 64 cells switch at N = 15
+                                     (15, (2, 2, 96)), (16, (2, 2, 96)), (16, (2, 1, 128))])
 def test_window_depth_threshold(N, shape):
-    """The sweeps take two target degrees per pass up to N = 20 and the
-    per-type depth above (three for FP64; FP32 three where x neighbours are
-    loaded): both sides of the switch, whole-row and loaded rows, FP64 and
-    FP32 against the oracle."""
+    """The sweeps take two target degrees per pass up to N = 20 (N = 15 on
+    rows longer than 64 cells) and the per-type depth above (three for FP64;
+    FP32 three where x neighbours are loaded): both sides of the switch,
+    whole-row and loaded rows, FP64 and FP32 against the oracle."""
     sa, ss, q, u = rand_problem(N, shape, 70 + N)
     h, dt = 0.1, 0.04
     ref = st.run(st.Setup(N, shape, h, dt, sa, ss, q), u, 2)
