@@ -637,13 +637,21 @@ template <> struct MinWaves<float> { static constexpr int v = PM_WPE32; };
 #ifndef PM_CHUNK_TILES2
 #define PM_CHUNK_TILES2 1
 #endif
+// resident waves asked for the FP32 forward sweeps with loaded x neighbours
+// (one cell per lane): 6 keeps depth 3 at 80 VGPRs without spills (5
+// otherwise); P39 160^3 odd + even 18.07 vs 18.16 ms, P19 500^3 147.7 vs
+// 149.1, P7 160^3 0.866 vs 0.901
+#ifndef PM_WPE32N
+#define PM_WPE32N 6
+#endif
 // resident waves asked for the FP64 forward sweeps with loaded x neighbours
 #ifndef PM_WPE64N
 #define PM_WPE64N 1
 #endif
-template <class T, int MODE, bool ANI, int XM>
+template <class T, int MODE, bool ANI, int XM, int CPL>
 constexpr int min_waves() {
     if (MODE == kFwd && XM == kXLoad && !ANI && std::is_same<T, double>::value) return PM_WPE64N;
+    if (MODE == kFwd && XM == kXLoad && !ANI && std::is_same<T, float>::value && CPL == 1) return PM_WPE32N;
     if (MODE == kFwd) return XM == kXRow && !ANI ? MinWaves<T>::v : 1;
     if (!std::is_same<T, double>::value || ANI) return 1;
     return MODE == kAdjTgt ? PM_WPE64_ADJ : PM_WPE64_DUAL;
@@ -658,7 +666,7 @@ constexpr int min_waves() {
 // come (XMode), in every mode: the push phase is the same forward-shaped
 // stencil for the transposed sweeps.
 template <class T, int K, int TPB, int CPL, int MODE, bool ANI, int XM>
-__global__ void __launch_bounds__(TPB, (min_waves<T, MODE, ANI, XM>()))
+__global__ void __launch_bounds__(TPB, (min_waves<T, MODE, ANI, XM, CPL>()))
 k_sweep_win(T* __restrict__ pool, StateOffs so, double* __restrict__ gp,
             const double* __restrict__ tab, const float* __restrict__ tabf,
             const int2* __restrict__ src, const int2* __restrict__ tgt,
