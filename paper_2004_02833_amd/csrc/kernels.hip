@@ -637,6 +637,15 @@ template <> struct MinWaves<float> { static constexpr int v = PM_WPE32; };
 #ifndef PM_CHUNK_TILES2
 #define PM_CHUNK_TILES2 1
 #endif
+// and at depth 2 (FP64: 5 waves spill 56 B, so the compiler's choice; BF16
+// two cells per lane: 6 waves at 80 VGPRs, odd + even sweep P39 64^3 0.694
+// vs 0.733 ms, 160^3 10.22 vs 10.62, P19 500^3 95.3 vs 108.6; 7 spill)
+#ifndef PM_WPE64N2
+#define PM_WPE64N2 1
+#endif
+#ifndef PM_WPE16N2
+#define PM_WPE16N2 6
+#endif
 // resident waves asked for the FP32 forward sweeps with loaded x neighbours
 // (one cell per lane): 6 keeps depth 3 at 80 VGPRs without spills (5
 // otherwise); P39 160^3 odd + even 18.07 vs 18.16 ms, P19 500^3 147.7 vs
@@ -648,8 +657,10 @@ template <> struct MinWaves<float> { static constexpr int v = PM_WPE32; };
 #ifndef PM_WPE64N
 #define PM_WPE64N 1
 #endif
-template <class T, int MODE, bool ANI, int XM, int CPL>
+template <class T, int K, int MODE, bool ANI, int XM, int CPL>
 constexpr int min_waves() {
+    if (MODE == kFwd && XM == kXLoad && !ANI && std::is_same<T, double>::value && K == 2) return PM_WPE64N2;
+    if (MODE == kFwd && XM == kXLoad && !ANI && std::is_same<T, bf16s>::value && K == 2) return PM_WPE16N2;
     if (MODE == kFwd && XM == kXLoad && !ANI && std::is_same<T, double>::value) return PM_WPE64N;
     if (MODE == kFwd && XM == kXLoad && !ANI && std::is_same<T, float>::value && CPL == 1) return PM_WPE32N;
     if (MODE == kFwd) return XM == kXRow && !ANI ? MinWaves<T>::v : 1;
@@ -666,7 +677,7 @@ constexpr int min_waves() {
 // come (XMode), in every mode: the push phase is the same forward-shaped
 // stencil for the transposed sweeps.
 template <class T, int K, int TPB, int CPL, int MODE, bool ANI, int XM>
-__global__ void __launch_bounds__(TPB, (min_waves<T, MODE, ANI, XM, CPL>()))
+__global__ void __launch_bounds__(TPB, (min_waves<T, K, MODE, ANI, XM, CPL>()))
 k_sweep_win(T* __restrict__ pool, StateOffs so, double* __restrict__ gp,
             const double* __restrict__ tab, const float* __restrict__ tabf,
             const int2* __restrict__ src, const int2* __restrict__ tgt,
