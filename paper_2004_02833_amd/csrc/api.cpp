@@ -516,9 +516,10 @@ int pm_init_cells(int N, int nx, int ny, int nz, double dx, double dy, double dz
     TRY(dmalloc(&C.plane64, sizeof(double) * (size_t)ncell, "plane"));
     TRY(dmalloc(&C.red, sizeof(double) * (C.npart + 1), "reduction"));
     TRY(dmalloc(&C.redc, sizeof(unsigned long long) * (C.npart + 1), "reduction"));
-    TRY(build_window_tables(pm::win_depth(C.prec, nx, N), C.win, &C.win_mem));
+    const int kwin = pm::win_depth(C.prec, nx, N, C.aniso);
+    TRY(build_window_tables(kwin, C.win, &C.win_mem));
 
-    if (C.prec != PM_BF16 && pm::adj_depth(C.prec) != pm::win_depth(C.prec, nx, N)) {
+    if (C.prec != PM_BF16 && pm::adj_depth(C.prec) != kwin) {
         TRY(build_window_tables(pm::adj_depth(C.prec), C.wadj, &C.adj_mem));
     } else {
         C.wadj[0] = C.win[0];

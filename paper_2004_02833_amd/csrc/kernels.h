@@ -56,8 +56,9 @@ struct WinArgs {
 };
 
 // Target degrees per pass of the forward sweeps (for a storage precision,
-// row length nx and moment order N) and of the transposed ones (pm_grad).
-int win_depth(int prec, int nx, int N);
+// row length nx, moment order N and anisotropic scattering) and of the
+// transposed ones (pm_grad).
+int win_depth(int prec, int nx, int N, bool aniso);
 int adj_depth(int prec);
 
 // Anisotropic scattering: gl = device array of g_0 .. g_N (g_0 = 1), or

@@ -52,6 +52,10 @@
 #endif
 // BF16 (all orders): P39 64^3 odd + even sweep 0.717 vs 0.832 ms at depth
 // 2 / 3, 160^3 10.41 vs 10.51, P19 500^3 105.4 vs 106.0
+// anisotropic FP64 (P39 64^3 odd + even sweep 2.242 vs 2.359 ms at depth 2 / 3)
+#ifndef PM_WIN_K64A
+#define PM_WIN_K64A 2
+#endif
 #ifndef PM_WIN_K16
 #define PM_WIN_K16 2
 #endif
@@ -1036,7 +1040,8 @@ static_assert(PM_ADJ_K64 >= 2 && PM_ADJ_K64 <= 3 && PM_ADJ_K32 >= 2 && PM_ADJ_K3
                   PM_WIN_K64 >= 2 && PM_WIN_K64 <= PM_MAX_K && PM_WIN_K32 >= 2 &&
                   PM_WIN_K32 <= PM_MAX_K && PM_WIN_K32R >= 2 && PM_WIN_K32R <= PM_MAX_K &&
                   PM_WIN_KLOW >= 2 && PM_WIN_KLOW <= PM_MAX_K && PM_MAX_K <= 4 &&
-                  PM_WIN_K64R >= 2 && PM_WIN_K64R <= PM_MAX_K,
+                  PM_WIN_K64R >= 2 && PM_WIN_K64R <= PM_MAX_K && PM_WIN_K64A >= 2 &&
+                  PM_WIN_K64A <= PM_MAX_K,
               "forward FP64 and FP32 sweeps are instantiated for depths 2..PM_MAX_K, "
               "the transposed ones for 2 and 3");
 
@@ -1049,8 +1054,11 @@ static_assert(PM_ADJ_K64 >= 2 && PM_ADJ_K64 <= 3 && PM_ADJ_K32 >= 2 && PM_ADJ_K3
 #define PM_ROW2_NMAX 10
 #endif
 
-int win_depth(int prec, int nx, int N) {
+int win_depth(int prec, int nx, int N, bool aniso) {
     if (prec == kBF16) return PM_WIN_K16;
+    // anisotropic FP64: the per-degree factors of K target degrees fill
+    // (8K + 1) LDS rows of 2 KB; depth 3 (50 KB) leaves 3 workgroups per CU
+    if (prec == kF64 && aniso) return PM_WIN_K64A;
     // rows longer than 64 cells (chunk or segment tiles), except FP32 rows of
     // 128 cells at two cells per lane, take the deeper passes from a lower N
     const bool long_rows = nx > 64 && !(prec == kF32 && nx == 128 && N <= PM_ROW2_NMAX);
@@ -1137,7 +1145,7 @@ static void launch_fwd(void* pool, StateOffs so, const double* tab, const float*
 hipError_t launch_sweep_win(int prec, void* pool, StateOffs so, const double* tab, const float* tabf,
                             int rowbase,
                             Aniso an, WinArgs a, GridDesc g, hipStream_t st) {
-    if (a.K != win_depth(prec, g.nx, a.N)) return hipErrorInvalidValue;
+    if (a.K != win_depth(prec, g.nx, a.N, an.gl != nullptr)) return hipErrorInvalidValue;
     // several cells per lane need whole lane groups within every row
     // FP64 and FP32 sweeps come in depths 2 and 3
     if (prec == kF64) {
