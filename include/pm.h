@@ -179,8 +179,9 @@ int pm_check(double* max_abs, long long* n_nonfinite);
  * capture, tight stepping loops, harnesses that forbid hipMalloc): pm_check
  * without allocation or host synchronisation.  The per-block partial
  * results live in the library's static device scratch (room for 1024
- * partials per GPU, held until the process ends; this call uses 256, for
- * any grid size: the reduction strides over the state).  Writes the float64
+ * partials per GPU, held until the process ends; this call uses all 1024,
+ * as pm_check does, for any grid size: the reduction strides over the
+ * state).  Writes the float64
  * maximum of |u| over all moments and cells to *dev_max_abs and the number
  * of non-finite values (unsigned 64-bit) to *dev_nonfinite, both device
  * pointers owned by the caller, queued on the bound stream with kernels

@@ -76,7 +76,8 @@ struct Ctx {
     double* plane64 = nullptr;
     double* red = nullptr;
     unsigned long long* redc = nullptr;
-    int npart = 256;
+    int npart = 256;   // partial sums of pm_total (its rounding depends on it)
+    int ncheck = 1024; // partial results of pm_check / pm_check_noalloc
     hipStream_t own = nullptr;
     int cfl_warn = 0;
     int ck = 0;
@@ -514,8 +515,8 @@ int pm_init_cells(int N, int nx, int ny, int nz, double dx, double dy, double dz
     if (ftab) TRY(dmalloc(&C.tabf, sizeof(float) * pm::kTabRows * (size_t)ncell, "float tables"));
     if (C.aniso) TRY(dmalloc(&C.gl, sizeof(double) * gl.size(), "scattering moments"));
     TRY(dmalloc(&C.plane64, sizeof(double) * (size_t)ncell, "plane"));
-    TRY(dmalloc(&C.red, sizeof(double) * (C.npart + 1), "reduction"));
-    TRY(dmalloc(&C.redc, sizeof(unsigned long long) * (C.npart + 1), "reduction"));
+    TRY(dmalloc(&C.red, sizeof(double) * (std::max(C.npart, C.ncheck) + 1), "reduction"));
+    TRY(dmalloc(&C.redc, sizeof(unsigned long long) * (C.ncheck + 1), "reduction"));
     const int kwin = pm::win_depth(C.prec, nx, N, C.aniso);
     TRY(build_window_tables(kwin, C.win, &C.win_mem));
 
@@ -818,12 +819,12 @@ int pm_total(double* out) {
 int pm_check(double* max_abs, long long* n_nonfinite) {
     if (!C.live) return fail(PM_ESTATE, "no context: call pm_init first");
     hipStream_t s = C.stream();
-    HIPCHK(pm::launch_check(C.prec, C.u, C.V, C.g, C.red, C.redc, C.npart, C.red + C.npart,
-                            C.redc + C.npart, s));
+    HIPCHK(pm::launch_check(C.prec, C.u, C.V, C.g, C.red, C.redc, C.ncheck, C.red + C.ncheck,
+                            C.redc + C.ncheck, s));
     double m = 0;
     unsigned long long k = 0;
-    HIPCHK(hipMemcpyAsync(&m, C.red + C.npart, sizeof(double), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipMemcpyAsync(&k, C.redc + C.npart, sizeof(k), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(&m, C.red + C.ncheck, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(&k, C.redc + C.ncheck, sizeof(k), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     if (max_abs) *max_abs = m;
     if (n_nonfinite) *n_nonfinite = (long long)k;
@@ -834,7 +835,7 @@ int pm_check(double* max_abs, long long* n_nonfinite) {
 int pm_check_noalloc(void* dev_max_abs, void* dev_nonfinite) {
     if (!C.live) return fail(PM_ESTATE, "no context: call pm_init first");
     if (!dev_max_abs || !dev_nonfinite) return fail(PM_EINVAL, "output pointers must not be NULL");
-    const int npart = C.npart;
+    const int npart = C.ncheck;
     if (npart > pm::scratch_partials())
         return fail(PM_EINVAL, "pm_check_noalloc: " + std::to_string(npart) + " partial results exceed the " +
                                    std::to_string(pm::scratch_partials()) + " of the static scratch");

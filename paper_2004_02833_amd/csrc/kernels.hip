@@ -1310,22 +1310,61 @@ hipError_t launch_sum(int prec, const void* plane, long long n, double* part, in
     return hipGetLastError();
 }
 
+// Largest |u| and count of non-finite values over the first nplanes planes.
+// Planes are walked one after another (no division per element); within a
+// plane every thread reads 16 bytes at a time (planes start 64-element
+// aligned), the last ncell mod VEC cells one by one.
+template <class T>
+__device__ __forceinline__ void check_vals(const uint4& w, double& m, unsigned long long& k) {
+    constexpr int VEC = 16 / sizeof(T);
+    double v[VEC];
+    if constexpr (std::is_same<T, double>::value) {
+        v[0] = __hiloint2double((int)w.y, (int)w.x);
+        v[1] = __hiloint2double((int)w.w, (int)w.z);
+    } else if constexpr (std::is_same<T, float>::value) {
+        v[0] = __uint_as_float(w.x);
+        v[1] = __uint_as_float(w.y);
+        v[2] = __uint_as_float(w.z);
+        v[3] = __uint_as_float(w.w);
+    } else {
+        const uint32_t q[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            v[2 * i] = bf_lo(q[i]);
+            v[2 * i + 1] = bf_hi(q[i]);
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < VEC; ++i) {
+        if (!isfinite(v[i]))
+            ++k;
+        else
+            m = fmax(m, fabs(v[i]));
+    }
+}
+
 template <class T>
 __global__ void k_check_partial(const T* __restrict__ u, int nplanes, GridDesc g,
                                 double* __restrict__ pmax, unsigned long long* __restrict__ pcnt) {
+    constexpr int VEC = 16 / sizeof(T);
     __shared__ double shm[256];
     __shared__ unsigned long long shc[256];
     double m = 0.0;
     unsigned long long k = 0;
-    const long long total = (long long)nplanes * g.ncell;
-    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < total;
-         i += (long long)gridDim.x * blockDim.x) {
-        const long long pl = i / g.ncell, c = i - pl * g.ncell;
-        const double v = (double)ld(u + pl * g.pstride + c);
-        if (!isfinite(v))
-            ++k;
-        else
-            m = fmax(m, fabs(v));
+    const long long t0 = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    const long long nv = g.ncell / VEC, tail = g.ncell - nv * VEC;
+    for (int pl = 0; pl < nplanes; ++pl) {
+        const T* p = u + (long long)pl * g.pstride;
+#pragma unroll 2
+        for (long long j = t0; j < nv; j += stride) check_vals<T>(*(const uint4*)(p + j * VEC), m, k);
+        if (t0 < tail) {
+            const double v = (double)ld(p + nv * VEC + t0);
+            if (!isfinite(v))
+                ++k;
+            else
+                m = fmax(m, fabs(v));
+        }
     }
     shm[threadIdx.x] = m;
     shc[threadIdx.x] = k;
