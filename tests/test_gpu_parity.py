@@ -322,3 +322,38 @@ def test_window_depth_threshold(N, shape):
         e = relerr(gpu_run(N, shape, h, dt, sa, ss, q, u, 2, prec=prec), ref)
         say("depth threshold N=%d %s prec %d err %.2e" % (N, shape, prec, e))
         assert e <= tol, prec
+
+
+@pytest.mark.parametrize("prec", [pm.PM_FP64, pm.PM_FP32, pm.PM_BF16])
+@pytest.mark.parametrize("shape", [(5, 3, 7), (1, 1, 33), (2, 3, 64)])
+def test_check_against_readback(prec, shape):
+    """pm_check (largest |u|, count of non-finite values) against the same
+    figures taken from the stored state read back through pm_read, in every
+    storage form, on grids whose cell count leaves a tail after the 16-byte
+    loads of the check (non-finite and largest values placed in that tail,
+    at the first cell and inside)."""
+    N = 2
+    V = (N + 1) ** 2
+    nz, ny, nx = shape
+    ncell = nz * ny * nx
+    rng = np.random.default_rng(90 + ncell + prec)
+    gpu_init(N, shape, 0.2, 0.05, rng.uniform(0, 1, shape), rng.uniform(0, 1, shape), prec=prec)
+    try:
+        for i in range(V):
+            plane = rng.normal(size=ncell)
+            if i == 0:
+                plane[-1] = 7.5      # the largest magnitude, in the last cell
+            if i == 4:
+                plane[-1] = np.nan
+            if i == 8:
+                plane[0] = np.inf
+                plane[ncell // 2] = -np.inf
+            pm.pm_write(i, plane.reshape(shape))
+        m, k = pm.pm_check()
+        back = np.stack([pm.pm_read(i) for i in range(V)])
+        finite = np.isfinite(back)
+        say("check %s prec %d: max %r count %d" % (shape, prec, m, k))
+        assert k == int((~finite).sum()) == 3
+        assert m == float(np.abs(back[finite]).max()) == 7.5
+    finally:
+        pm.pm_finalize()
